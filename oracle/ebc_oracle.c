@@ -468,12 +468,20 @@ int ora_rle_decode(const uint16_t* val, const uint32_t* len, uint64_t r, uint64_
     return pos == n ? ORA_OK : ORA_ERR_ARCHIVE;
 }
 
-/* D3: fuse quant-codes and outliers, q' = q - r then q'[idx] = delta. */
+/* D3: fuse quant-codes and outliers, q' = q - r then q'[idx] = delta.
+   Code 0 is the outlier placeholder (Sec. IV-B.1), so the archive is only
+   consistent when the outlier list names every code-0 position exactly once:
+   indices ascending, each pointing at a 0, and as many entries as zeros. */
 int ora_fuse(const uint16_t* q, uint64_t n, uint32_t n_bins, const uint32_t* oidx,
              const int32_t* oval, uint64_t no, int32_t* qp)
 {
     int32_t r = (int32_t)(n_bins / 2);
-    for (uint64_t i = 0; i < n; ++i) qp[i] = (int32_t)q[i] - r;
+    uint64_t zeros = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        qp[i] = (int32_t)q[i] - r;
+        zeros += q[i] == 0;
+    }
+    if (zeros != no) return ORA_ERR_ARCHIVE;
     for (uint64_t k = 0; k < no; ++k) {
         if (oidx[k] >= n) return ORA_ERR_ARCHIVE;
         if (k > 0 && oidx[k] <= oidx[k - 1]) return ORA_ERR_ARCHIVE;

@@ -1,0 +1,1059 @@
+// capi.hip -- C ABI of the compressor: validation, planning, workspace
+// carving and the kernel sequences for compression and decompression.
+//
+// Every call is a batch: fields are grouped by (rank, 16-byte row alignment)
+// so each construct / reconstruct launch is specialised, and every other
+// kernel covers all fields in one grid.  The host never looks at data between
+// kernels: the codec decision, the outlier count, section offsets and the
+// archive size are computed and consumed on the device; the plain compress
+// call synchronises once at the end to return the size.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/ebc.h"
+#include "ebc_dev.h"
+#include "ebc_launch.h"
+
+using namespace ebc;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int status, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(EBC_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+inline uint64_t a256(uint64_t v) { return (v + 255u) & ~(uint64_t)255u; }
+inline uint64_t a16h(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+inline uint32_t p2ceil(uint32_t v)
+{
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// ------------------------------------------------------------------ params
+struct Params {
+    int eb_mode, codec;
+    double eb;
+    uint32_t n_bins, hc;
+};
+
+int check_params(const ebc_params* p, Params* out)
+{
+    if (!p) return fail(EBC_ERR_ARG, "params is NULL");
+    if (p->eb_mode != EBC_EB_ABS && p->eb_mode != EBC_EB_REL) return fail(EBC_ERR_ARG, "bad eb_mode");
+    if (p->codec < EBC_CODEC_AUTO || p->codec > EBC_CODEC_RLE) return fail(EBC_ERR_ARG, "bad codec");
+    if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return fail(EBC_ERR_EB, "eb must be finite and > 0");
+    if (p->n_bins < 4 || p->n_bins > 65536 || (p->n_bins & 1))
+        return fail(EBC_ERR_BINS, "n_bins must be even in [4, 65536]");
+    const uint32_t hc = p->huff_chunk ? p->huff_chunk : 1024u;
+    if (hc < 64 || hc > 65536 || (hc & (hc - 1)))
+        return fail(EBC_ERR_ARG, "huff_chunk must be a power of two in [64, 65536]");
+    if (p->n_bins > kMaxBins)
+        return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented on this GPU path", kMaxBins);
+    if (hc > kMaxHc) return fail(EBC_ERR_UNSUPPORTED, "huff_chunk > %u not implemented", kMaxHc);
+    out->eb_mode = p->eb_mode;
+    out->codec = p->codec;
+    out->eb = p->eb;
+    out->n_bins = p->n_bins;
+    out->hc = hc;
+    return EBC_OK;
+}
+
+int check_dims(int rank, const uint64_t dims[3], uint64_t* n)
+{
+    if (!dims) return fail(EBC_ERR_ARG, "dims is NULL");
+    if (rank < 1 || rank > 3) return fail(EBC_ERR_DIMS, "rank must be 1, 2 or 3");
+    for (int k = 0; k < 3; ++k) {
+        if (dims[k] == 0) return fail(EBC_ERR_DIMS, "zero dimension");
+        if (k >= rank && dims[k] != 1) return fail(EBC_ERR_DIMS, "unused dimension must be 1");
+        if (dims[k] >= (1ull << 32)) return fail(EBC_ERR_DIMS, "dimension too large");
+    }
+    uint64_t p = dims[0] * dims[1];
+    if (p >= (1ull << 32)) return fail(EBC_ERR_DIMS, "N >= 2^32");
+    p *= dims[2];
+    if (p >= (1ull << 32)) return fail(EBC_ERR_DIMS, "N >= 2^32");
+    *n = p;
+    return EBC_OK;
+}
+
+// ------------------------------------------------------------------ geometry
+// Lanes along x for a construct / reconstruct wave-tile: enough 4-wide quads
+// to cover nx (no idle lanes on narrow fields), at least one chunk row.
+uint32_t choose_lx(int rank, uint64_t nx)
+{
+    if (rank == 1) return 64;
+    const uint32_t minlx = rank == 2 ? 4u : 2u;
+    const uint32_t want = p2ceil((uint32_t)std::min<uint64_t>((nx + 3) / 4, 64));
+    return std::max(minlx, std::min(64u, want));
+}
+
+struct Geo {
+    int rank;
+    uint64_t nx, ny, nz, n;
+    uint32_t lx, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
+    uint32_t n_seg, range_units, ow_units, n_hch, hwg_units, hdwg_units, n_rt;
+};
+
+Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc, uint32_t lx_override)
+{
+    Geo g = {};
+    g.rank = rank;
+    g.nx = dims[0], g.ny = dims[1], g.nz = dims[2];
+    g.n = g.nx * g.ny * g.nz;
+    g.lx = lx_override ? lx_override : choose_lx(rank, g.nx);
+    if (rank == 1) {
+        g.nxb = 1, g.nyb = 1, g.nzb = 1;
+        g.n_wave_tiles = cdiv(g.n, 1024);
+        g.n_seg = cdiv(g.n, 256);
+    } else {
+        const uint32_t xs = 4 * g.lx, G = kWave / g.lx;
+        const uint32_t cy = rank == 2 ? 16 : 8, cz = rank == 2 ? 1 : 8;
+        g.nxb = cdiv(g.nx, xs);
+        g.nyb = cdiv(g.ny, (uint64_t)cy * G);
+        g.nzb = cdiv(g.nz, cz);
+        g.n_wave_tiles = g.nxb * g.nyb * g.nzb;
+        g.n_seg = (uint32_t)(g.nz * g.ny * g.nxb);
+    }
+    g.wg_tiles = cdiv(g.n_wave_tiles, kWavesPerBlock);
+    g.range_units = cdiv(g.n, kRangeUnit);
+    g.ow_units = outlier_write_units(g.n_seg);
+    g.n_hch = cdiv(g.n, hc);
+    g.hwg_units = cdiv(g.n_hch, huff_cpw(hc));
+    g.hdwg_units = cdiv(g.n_hch, kBlock);
+    g.n_rt = cdiv(g.n, kRleTile);
+    return g;
+}
+
+// ------------------------------------------------------------------ workspace
+struct Bump {
+    uint8_t* base;
+    uint64_t off = 0;
+    template <class T>
+    T* take(uint64_t bytes)
+    {
+        T* p = base ? (T*)(base + off) : nullptr;
+        off = a256(off + std::max<uint64_t>(bytes, 1));
+        return p;
+    }
+};
+
+struct Batch {
+    int nf = 0;
+    std::vector<FieldDesc> fd;    // sorted by (rank, vec)
+    std::vector<int> order;       // fd[k] is caller field order[k]
+    struct Group {
+        int rank;
+        bool vec;
+        int first, count;
+        uint32_t wg_tiles;
+    };
+    std::vector<Group> groups;
+    uint32_t tot_range = 0, tot_seg = 0, tot_ow = 0, tot_hch = 0, tot_hwg = 0, tot_hdwg = 0,
+             tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0;
+    uint32_t max_rle_units = 0;
+    FieldDesc* d_fd = nullptr;
+    FieldDyn* d_dyn = nullptr;
+    uint32_t *d_seg = nullptr, *d_wcnt = nullptr, *d_rcnt = nullptr, *d_starts = nullptr,
+             *d_tmp = nullptr;
+    uint8_t* d_tabs = nullptr;
+    uint64_t* d_result = nullptr;
+    uint64_t ws_bytes = 0;
+};
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Group fields by (rank, vec) and assign every work-unit base.
+void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec)
+{
+    const int nf = B.nf;
+    std::vector<int> idx(nf);
+    for (int i = 0; i < nf; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        const int ka = geo[a].rank * 2 + (vec[a] ? 1 : 0), kb = geo[b].rank * 2 + (vec[b] ? 1 : 0);
+        return ka < kb;
+    });
+    B.order = idx;
+    B.groups.clear();
+    for (int k = 0; k < nf; ++k) {
+        const Geo& g = geo[idx[k]];
+        const bool v = vec[idx[k]];
+        if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v)
+            B.groups.push_back({g.rank, v, k, 0, 0});
+        Batch::Group& G = B.groups.back();
+        FieldDesc& d = B.fd[k];
+        d.wg_base = G.wg_tiles;
+        d.wg_tiles = g.wg_tiles;
+        G.wg_tiles += g.wg_tiles;
+        G.count++;
+        d.range_base = B.tot_range, d.range_units = g.range_units, B.tot_range += g.range_units;
+        d.seg_base = B.tot_seg, d.n_seg = g.n_seg, B.tot_seg += g.n_seg;
+        d.ow_base = B.tot_ow, d.ow_units = g.ow_units, B.tot_ow += g.ow_units;
+        d.hch_base = B.tot_hch, d.n_hch = g.n_hch, B.tot_hch += g.n_hch;
+        d.hwg_base = B.tot_hwg, d.hwg_units = g.hwg_units, B.tot_hwg += g.hwg_units;
+        d.hdwg_base = B.tot_hdwg, d.hdwg_units = g.hdwg_units, B.tot_hdwg += g.hdwg_units;
+        d.rt_base = B.tot_rt, d.n_rt = g.n_rt, B.tot_rt += g.n_rt;
+        B.max_rle_units = std::max(B.max_rle_units, cdiv(g.n, kBlock));
+    }
+}
+
+void fill_geometry(FieldDesc& d, const Geo& g, bool vec)
+{
+    d.n = g.n;
+    d.nx = (uint32_t)g.nx, d.ny = (uint32_t)g.ny, d.nz = (uint32_t)g.nz;
+    d.rank = g.rank;
+    d.lx = g.lx;
+    d.nxb = g.nxb, d.nyb = g.nyb, d.nzb = g.nzb;
+    d.n_wave_tiles = g.n_wave_tiles;
+    d.vec = vec ? 1u : 0u;
+}
+
+// Compression plan: geometry, bases and workspace carving (base == nullptr
+// only sizes the workspace).
+struct CompressIn {
+    const float* in;
+    int rank;
+    uint64_t dims[3];
+    void* out;
+    uint64_t cap;
+};
+
+void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P, uint8_t* ws,
+                   uint32_t lx_override = 0)
+{
+    B.nf = (int)fin.size();
+    B.fd.assign(B.nf, FieldDesc{});
+    std::vector<Geo> geo(B.nf);
+    std::vector<bool> vec(B.nf);
+    for (int i = 0; i < B.nf; ++i) {
+        geo[i] = make_geo(fin[i].rank, fin[i].dims, P.hc, lx_override);
+        vec[i] = aligned16(fin[i].in) && (fin[i].rank == 1 || geo[i].nx % 4 == 0);
+    }
+    assign_bases(B, geo, vec);
+    Bump bp{ws};
+    B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
+    B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
+    B.d_seg = bp.take<uint32_t>(4ull * (B.tot_seg + 1));
+    B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
+    B.d_rcnt = bp.take<uint32_t>(4ull * (B.tot_rt + 1));
+    const uint32_t big = std::max({B.tot_seg, B.tot_hch, B.tot_rt});
+    B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(big));
+    B.d_result = bp.take<uint64_t>(16);
+    for (int k = 0; k < B.nf; ++k) {
+        const int i = B.order[k];
+        const Geo& g = geo[i];
+        FieldDesc& d = B.fd[k];
+        fill_geometry(d, g, vec[i]);
+        d.n_bins = P.n_bins;
+        d.hc = P.hc;
+        d.eb_mode = P.eb_mode;
+        d.codec_req = P.codec;
+        d.eb = P.eb;
+        d.in = fin[i].in;
+        d.arc = (uint8_t*)fin[i].out;
+        d.arc_cap = fin[i].cap;
+        d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
+        d.q = bp.take<uint16_t>(2 * g.n);
+        d.dsc = bp.take<int32_t>(4 * g.n);
+        d.rstart = (uint32_t*)d.dsc;  // used only after the outliers are written
+        d.hist = bp.take<uint32_t>(4ull * P.n_bins);
+        d.hpart = bp.take<uint32_t>(4ull * P.n_bins * g.wg_tiles);
+        d.rpart = bp.take<uint32_t>(12ull * g.range_units);
+        d.code = bp.take<uint64_t>(8ull * P.n_bins);
+        d.len = bp.take<uint8_t>(P.n_bins);
+        d.hbits = bp.take<uint32_t>(4ull * g.n_hch);
+    }
+    B.ws_bytes = bp.off;
+}
+
+// ------------------------------------------------------------------ timing
+struct Timer {
+    ebc_stats* st;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    std::vector<const char*> names;
+    bool on;
+    Timer(ebc_stats* st_, hipStream_t s_) : st(st_), s(s_), on(st_ && (st_->flags & EBC_STATS_TIMING)) {}
+    void mark(const char* name)
+    {
+        if (!on || names.size() >= EBC_MAX_STAGES) return;
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        (void)hipEventRecord(e, s);
+        ev.push_back(e);
+        names.push_back(name);
+    }
+    // call after the stream has been synchronised
+    void finish()
+    {
+        if (!on) return;
+        mark("end");
+        (void)hipEventSynchronize(ev.back());
+        st->n_stages = 0;
+        for (size_t k = 0; k + 1 < ev.size(); ++k) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            st->stage_ms[k] = ms;
+            st->stage_name[k] = names[k];
+            st->n_stages = (uint32_t)(k + 1);
+        }
+    }
+    ~Timer()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+// ------------------------------------------------------------------ pipelines
+int enqueue_compress(Batch& B, const Params& P, hipStream_t s, Timer& T, bool debug_stop = false)
+{
+    const int nf = B.nf;
+    HIP_TRY(upload_descs(B.fd.data(), nf, B.d_fd, s));
+    T.mark("range");
+    HIP_TRY(launch_range(B.d_fd, nf, B.tot_range, s));
+    T.mark("params");
+    HIP_TRY(launch_params(B.d_fd, nf, s));
+    T.mark("construct");
+    for (const auto& G : B.groups)
+        HIP_TRY(launch_construct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, P.n_bins,
+                                 B.d_seg, s));
+    T.mark("hist_reduce");
+    HIP_TRY(launch_hist_reduce(B.d_fd, nf, P.n_bins, s));
+    T.mark("scan_outliers");
+    HIP_TRY(launch_scan(B.d_seg, B.tot_seg, B.d_tmp, s));
+    if (debug_stop) return EBC_OK;
+    T.mark("codebook");
+    HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, s));
+    T.mark("encode_count");
+    HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, s));
+    HIP_TRY(launch_rle_count(B.d_fd, nf, B.tot_rt, B.d_rcnt, s));
+    T.mark("encode_scan");
+    HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
+    HIP_TRY(launch_scan(B.d_rcnt, B.tot_rt, B.d_tmp, s));
+    T.mark("layout");
+    HIP_TRY(launch_layout(B.d_fd, nf, B.d_seg, B.d_wcnt, B.d_rcnt, s));
+    T.mark("outlier_write");
+    HIP_TRY(launch_outlier_write(B.d_fd, nf, B.tot_ow, B.d_seg, s));
+    T.mark("encode_write");
+    HIP_TRY(launch_huff_write(B.d_fd, nf, B.tot_hwg, P.hc, P.n_bins, B.d_wcnt, s));
+    HIP_TRY(launch_rle_write(B.d_fd, nf, B.tot_rt, B.d_rcnt, s));
+    HIP_TRY(launch_rle_len(B.d_fd, nf, B.max_rle_units, s));
+    T.mark("header");
+    HIP_TRY(launch_header(B.d_fd, nf, s));
+    return EBC_OK;
+}
+
+int compress_common(const std::vector<CompressIn>& fin, const ebc_params* p, void* d_ws,
+                    uint64_t ws_bytes, hipStream_t s, Batch& B, Params& P)
+{
+    int st = check_params(p, &P);
+    if (st) return st;
+    for (const auto& f : fin) {
+        uint64_t n;
+        if (!f.in || !f.out) return fail(EBC_ERR_ARG, "NULL field or output pointer");
+        st = check_dims(f.rank, f.dims, &n);
+        if (st) return st;
+    }
+    if (!d_ws) return fail(EBC_ERR_ARG, "workspace is NULL");
+    Batch sizing;
+    plan_compress(sizing, fin, P, nullptr);
+    if (ws_bytes < sizing.ws_bytes)
+        return fail(EBC_ERR_WS_TOO_SMALL, "workspace %llu < required %llu",
+                    (unsigned long long)ws_bytes, (unsigned long long)sizing.ws_bytes);
+    plan_compress(B, fin, P, (uint8_t*)d_ws);
+    return EBC_OK;
+}
+
+void fill_stats(ebc_stats* st, const FieldDyn& d, uint64_t n)
+{
+    if (!st) return;
+    st->codec = d.codec;
+    st->n_elems = n;
+    st->n_outliers = d.n_out;
+    st->n_runs = d.n_runs;
+    st->n_words = d.n_words;
+    st->huff_bits = d.huff_bits;
+    st->out_bytes = d.total;
+    st->eb_abs = d.eb_abs;
+    st->ebx2 = d.ebx2;
+    st->value_min = d.mn;
+    st->value_max = d.mx;
+}
+
+// ------------------------------------------------------------------ decompress plan
+struct Header {
+    int rank, codec, eb_mode;
+    uint32_t n_bins, hc;
+    uint64_t dims[3];
+    uint32_t chunk[3];
+    double eb, eb_abs, ebx2;
+    float cval;
+    uint64_t n_out, n_a, n_words, total;
+    uint64_t n;
+    uint64_t off_bits, off_words, off_val, off_rlen, off_oidx, off_oval;
+};
+
+int parse_header(const void* h, uint64_t bytes, Header* H)
+{
+    if (!h) return fail(EBC_ERR_ARG, "header is NULL");
+    if (bytes < kHdr) return fail(EBC_ERR_ARCHIVE, "archive shorter than its header");
+    const uint8_t* a = (const uint8_t*)h;
+    if (memcmp(a, "EBC1", 4) != 0) return fail(EBC_ERR_ARCHIVE, "bad magic");
+    uint16_t ver;
+    memcpy(&ver, a + 4, 2);
+    if (ver != 1) return fail(EBC_ERR_ARCHIVE, "unsupported version %u", ver);
+    H->rank = a[8], H->codec = a[9], H->eb_mode = a[10];
+    memcpy(&H->n_bins, a + 12, 4);
+    memcpy(H->dims, a + 16, 24);
+    memcpy(H->chunk, a + 40, 12);
+    memcpy(&H->hc, a + 52, 4);
+    memcpy(&H->eb, a + 56, 8);
+    memcpy(&H->eb_abs, a + 64, 8);
+    memcpy(&H->ebx2, a + 72, 8);
+    memcpy(&H->cval, a + 80, 4);
+    memcpy(&H->n_out, a + 88, 8);
+    memcpy(&H->n_a, a + 96, 8);
+    memcpy(&H->n_words, a + 104, 8);
+    memcpy(&H->total, a + 112, 8);
+    if (H->codec > 2) return fail(EBC_ERR_ARCHIVE, "bad codec byte");
+    if (H->rank < 1 || H->rank > 3) return fail(EBC_ERR_ARCHIVE, "bad rank");
+    uint64_t n;
+    if (check_dims(H->rank, H->dims, &n)) return fail(EBC_ERR_ARCHIVE, "bad dims");
+    H->n = n;
+    if (H->n_bins < 4 || H->n_bins > 65536 || (H->n_bins & 1)) return fail(EBC_ERR_ARCHIVE, "bad n_bins");
+    if (H->hc < 64 || H->hc > 65536 || (H->hc & (H->hc - 1))) return fail(EBC_ERR_ARCHIVE, "bad chunk");
+    if (H->codec == EBC_ARC_CONST) {
+        if (H->total != kHdr) return fail(EBC_ERR_ARCHIVE, "bad constant archive size");
+        return EBC_OK;
+    }
+    if (H->n_out > n) return fail(EBC_ERR_ARCHIVE, "outlier count exceeds N");
+    if (H->codec == EBC_ARC_HUFFMAN) {
+        const uint64_t nch = (n + H->hc - 1) / H->hc;
+        if (H->n_a != nch) return fail(EBC_ERR_ARCHIVE, "chunk count mismatch");
+        if (H->n_words > 2 * n + nch) return fail(EBC_ERR_ARCHIVE, "word count too large");
+        H->off_bits = a16h(kHdr + H->n_bins);
+        H->off_words = a16h(H->off_bits + 4 * nch);
+        H->off_oidx = a16h(H->off_words + 4 * H->n_words);
+    } else {
+        if (H->n_a > n || H->n_a == 0) return fail(EBC_ERR_ARCHIVE, "bad run count");
+        if (H->n_words != 0) return fail(EBC_ERR_ARCHIVE, "RLE archive with Huffman words");
+        H->off_val = kHdr;
+        H->off_rlen = a16h(kHdr + 2 * H->n_a);
+        H->off_oidx = a16h(H->off_rlen + 4 * H->n_a);
+    }
+    H->off_oval = a16h(H->off_oidx + 4 * H->n_out);
+    const uint64_t total = a16h(H->off_oval + 4 * H->n_out);
+    if (total != H->total) return fail(EBC_ERR_ARCHIVE, "section sizes do not add up");
+    return EBC_OK;
+}
+
+int header_supported(const Header& H)
+{
+    if (H.codec == EBC_ARC_CONST) return EBC_OK;
+    const uint32_t want[3][3] = {{256, 1, 1}, {16, 16, 1}, {8, 8, 8}};
+    for (int k = 0; k < 3; ++k)
+        if (H.chunk[k] != want[H.rank - 1][k])
+            return fail(EBC_ERR_UNSUPPORTED, "non-default Lorenzo chunk not implemented");
+    if (H.n_bins > kMaxBins) return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented", kMaxBins);
+    if (H.hc > kMaxHc) return fail(EBC_ERR_UNSUPPORTED, "huff_chunk > %u not implemented", kMaxHc);
+    return EBC_OK;
+}
+
+struct DecompressIn {
+    Header H;
+    const void* arc;
+    uint64_t size;
+    float* out;
+    uint64_t out_elems;
+};
+
+void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws,
+                     uint32_t lx_override = 0)
+{
+    B.nf = (int)din.size();
+    B.fd.assign(B.nf, FieldDesc{});
+    std::vector<Geo> geo(B.nf);
+    std::vector<bool> vec(B.nf);
+    for (int i = 0; i < B.nf; ++i) {
+        const Header& H = din[i].H;
+        geo[i] = make_geo(H.rank, H.dims, H.hc, lx_override);
+        vec[i] = aligned16(din[i].out) && (H.rank == 1 || geo[i].nx % 4 == 0);
+    }
+    assign_bases(B, geo, vec);
+    Bump bp{ws};
+    B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
+    B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
+    // per-codec unit counts (other codecs get zero units)
+    B.tot_hch = B.tot_hdwg = B.tot_rt = B.tot_runs = B.tot_sc = B.tot_rl = 0;
+    B.tot_range = 0;
+    for (int k = 0; k < B.nf; ++k) {
+        const DecompressIn& D = din[B.order[k]];
+        const Header& H = D.H;
+        FieldDesc& d = B.fd[k];
+        const Geo& g = geo[B.order[k]];
+        d.codec_hdr = H.codec;
+        const bool huff = H.codec == EBC_ARC_HUFFMAN, rle = H.codec == EBC_ARC_RLE,
+                   cst = H.codec == EBC_ARC_CONST;
+        d.hch_base = B.tot_hch, d.n_hch = huff ? g.n_hch : 0, B.tot_hch += d.n_hch;
+        d.hdwg_base = B.tot_hdwg, d.hdwg_units = huff ? g.hdwg_units : 0, B.tot_hdwg += d.hdwg_units;
+        d.rt_base = B.tot_rt, d.n_rt = rle ? g.n_rt : 0, B.tot_rt += d.n_rt;
+        d.rle_base = B.tot_runs, d.n_runs_hdr = rle ? (uint32_t)H.n_a : 0, B.tot_runs += d.n_runs_hdr;
+        d.rl_base = B.tot_rl, d.rl_units = cdiv(d.n_runs_hdr, kBlock), B.tot_rl += d.rl_units;
+        const uint32_t sc = cst ? 0 : cdiv(H.n_out, kBlock);
+        d.sc_base = B.tot_sc, d.sc_units = sc, B.tot_sc += sc;
+        d.range_base = B.tot_range, d.range_units = cst ? g.range_units : 0, B.tot_range += d.range_units;
+        if (cst) {
+            // no reconstruction work for a constant field
+            d.wg_tiles = 0;
+        }
+    }
+    // reconstruct groups: recount WG tiles without constant fields
+    for (auto& G : B.groups) {
+        G.wg_tiles = 0;
+        for (int k = G.first; k < G.first + G.count; ++k) {
+            FieldDesc& d = B.fd[k];
+            const Geo& g = geo[B.order[k]];
+            const uint32_t wt = d.codec_hdr == EBC_ARC_CONST ? 0 : g.wg_tiles;
+            d.wg_base = G.wg_tiles;
+            d.wg_tiles = wt;
+            G.wg_tiles += wt;
+        }
+    }
+    B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
+    B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
+    B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(std::max(B.tot_hch, B.tot_runs)));
+    B.d_tabs = bp.take<uint8_t>(dectab_bytes() * B.nf);
+    B.d_result = bp.take<uint64_t>(16);
+    for (int k = 0; k < B.nf; ++k) {
+        const DecompressIn& D = din[B.order[k]];
+        const Header& H = D.H;
+        const Geo& g = geo[B.order[k]];
+        FieldDesc& d = B.fd[k];
+        fill_geometry(d, g, vec[B.order[k]]);
+        d.n_bins = H.n_bins;
+        d.hc = H.hc;
+        d.eb_mode = H.eb_mode;
+        d.eb = H.eb;
+        d.outf = D.out;
+        d.arc = (uint8_t*)D.arc;
+        d.arc_cap = D.size;
+        d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
+        d.n_out_hdr = H.n_out;
+        d.n_words_hdr = H.n_words;
+        d.ebx2_hdr = H.ebx2;
+        d.cval = H.cval;
+        d.off_bits = H.off_bits, d.off_words = H.off_words, d.off_val = H.off_val;
+        d.off_rlen = H.off_rlen, d.off_oidx = H.off_oidx, d.off_oval = H.off_oval;
+        const bool cst = H.codec == EBC_ARC_CONST;
+        d.q = bp.take<uint16_t>(cst ? 0 : 2 * g.n);
+        d.dsc = bp.take<int32_t>(cst ? 0 : 4 * g.n);
+        d.zpart = bp.take<uint32_t>(4ull * std::max(d.wg_tiles, 1u));
+    }
+    B.ws_bytes = bp.off;
+}
+
+__global__ void k_words_check(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ woff)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const FieldDesc& fd = F[f];
+    if (fd.codec_hdr != ARC_HUFFMAN) return;
+    const uint32_t tot = woff[fd.hch_base + fd.n_hch] - woff[fd.hch_base];
+    if ((uint64_t)tot != fd.n_words_hdr) atomicMin(&fd.dyn->status, (int32_t)ST_ERR_ARCHIVE);
+}
+
+int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
+{
+    const int nf = B.nf;
+    HIP_TRY(upload_descs(B.fd.data(), nf, B.d_fd, s));
+    HIP_TRY(launch_dinit(B.d_fd, nf, s));
+    T.mark("decode_prep");
+    if (B.tot_hch) {
+        HIP_TRY(launch_huff_prep(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, s));
+        HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
+        hipLaunchKernelGGL(k_words_check, dim3((nf + 63) / 64), dim3(64), 0, s, B.d_fd, nf, B.d_wcnt);
+        HIP_TRY(hipGetLastError());
+        T.mark("dectab");
+        HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, s));
+        T.mark("huffman_decode");
+        HIP_TRY(launch_huff_decode(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, B.d_tabs, dectab_bytes(), s));
+    }
+    if (B.tot_runs) {
+        T.mark("rle_decode");
+        HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmp, B.tot_runs, s));
+    }
+    T.mark("outlier_scatter");
+    HIP_TRY(launch_outlier_scatter(B.d_fd, nf, B.tot_sc, s));
+    T.mark("reconstruct");
+    for (const auto& G : B.groups)
+        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, s));
+    T.mark("check");
+    HIP_TRY(launch_recon_check(B.d_fd, nf, s));
+    HIP_TRY(launch_fill_const(B.d_fd, nf, B.tot_range, s));
+    return EBC_OK;
+}
+
+int read_dyn(const Batch& B, std::vector<FieldDyn>& dyn, hipStream_t s)
+{
+    dyn.resize(B.nf);
+    HIP_TRY(hipMemcpyAsync(dyn.data(), B.d_dyn, sizeof(FieldDyn) * B.nf, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return EBC_OK;
+}
+
+int status_of(const FieldDyn& d)
+{
+    if (d.status == ST_OK) return EBC_OK;
+    switch (d.status) {
+    case ST_ERR_NONFINITE: return fail(EBC_ERR_NONFINITE, "NaN or Inf in the field");
+    case ST_ERR_EB_TOO_SMALL: return fail(EBC_ERR_EB_TOO_SMALL, "error bound below fp32 resolution of the field");
+    case ST_ERR_EB: return fail(EBC_ERR_EB, "error bound out of range");
+    case ST_ERR_OUT_TOO_SMALL: return fail(EBC_ERR_OUT_TOO_SMALL, "archive larger than the output buffer (%llu bytes needed)", (unsigned long long)d.total);
+    case ST_ERR_ARCHIVE: return fail(EBC_ERR_ARCHIVE, "archive content is inconsistent");
+    default: return fail(d.status, "device status %d", d.status);
+    }
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+int ebc_version(void) { return EBC_VERSION; }
+
+const char* ebc_status_string(int status)
+{
+    switch (status) {
+    case EBC_OK: return "ok";
+    case EBC_ERR_ARG: return "invalid argument";
+    case EBC_ERR_DIMS: return "invalid dimensions";
+    case EBC_ERR_EB: return "invalid error bound";
+    case EBC_ERR_EB_TOO_SMALL: return "error bound too small for fp32 output";
+    case EBC_ERR_BINS: return "invalid bin count";
+    case EBC_ERR_NONFINITE: return "non-finite value in field";
+    case EBC_ERR_OUT_TOO_SMALL: return "output buffer too small";
+    case EBC_ERR_WS_TOO_SMALL: return "workspace too small";
+    case EBC_ERR_ARCHIVE: return "corrupt or inconsistent archive";
+    case EBC_ERR_HIP: return "HIP runtime error";
+    case EBC_ERR_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+    }
+}
+
+const char* ebc_last_error(void) { return g_err; }
+
+int ebc_compress_bound(int rank, const uint64_t dims[3], const ebc_params* p, uint64_t* max_bytes)
+{
+    Params P;
+    uint64_t n;
+    if (!max_bytes) return fail(EBC_ERR_ARG, "max_bytes is NULL");
+    int st = check_dims(rank, dims, &n);
+    if (st) return st;
+    st = check_params(p, &P);
+    if (st && st != EBC_ERR_UNSUPPORTED) return st;
+    const uint32_t hc = p->huff_chunk ? p->huff_chunk : 1024u;
+    const uint64_t nch = (n + hc - 1) / hc;
+    uint32_t lb = 0;
+    while ((1ull << lb) < p->n_bins) ++lb;
+    const uint64_t huff = a16h(p->n_bins) + a16h(4 * nch) + a16h(4 * ((n * lb + 31) / 32 + nch));
+    const uint64_t rle = a16h(2 * n) + a16h(4 * n);
+    *max_bytes = kHdr + std::max(huff, rle) + a16h(4 * n) + a16h(4 * n);
+    return EBC_OK;
+}
+
+int ebc_compress_workspace_size(int rank, const uint64_t dims[3], const ebc_params* p, uint64_t* bytes)
+{
+    Params P;
+    uint64_t n;
+    if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
+    int st = check_dims(rank, dims, &n);
+    if (st) return st;
+    st = check_params(p, &P);
+    if (st) return st;
+    std::vector<CompressIn> fin(1);
+    fin[0] = {(const float*)nullptr, rank, {dims[0], dims[1], dims[2]}, nullptr, 0};
+    Batch B;
+    plan_compress(B, fin, P, nullptr);
+    *bytes = B.ws_bytes;
+    return EBC_OK;
+}
+
+int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+                 void* d_out, uint64_t out_cap, uint64_t* out_size, void* d_ws, uint64_t ws_bytes,
+                 void* stream, ebc_stats* stats)
+{
+    if (!out_size) return fail(EBC_ERR_ARG, "out_size is NULL");
+    *out_size = 0;
+    if (!dims) return fail(EBC_ERR_ARG, "dims is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(1);
+    fin[0] = {d_field, rank, {dims[0], dims[1], dims[2]}, d_out, out_cap};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(stats, s);
+    st = enqueue_compress(B, P, s, T);
+    if (st) return st;
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    T.finish();
+    fill_stats(stats, dyn[0], B.fd[0].n);
+    st = status_of(dyn[0]);
+    if (st) return st;
+    *out_size = dyn[0].total;
+    return EBC_OK;
+}
+
+int ebc_compress_async(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+                       void* d_out, uint64_t out_cap, uint64_t* d_result, void* d_ws,
+                       uint64_t ws_bytes, void* stream)
+{
+    if (!d_result || !dims) return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(1);
+    fin[0] = {d_field, rank, {dims[0], dims[1], dims[2]}, d_out, out_cap};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(nullptr, s);
+    st = enqueue_compress(B, P, s, T);
+    if (st) return st;
+    HIP_TRY(launch_result(B.d_fd, d_result, s));
+    return EBC_OK;
+}
+
+int ebc_archive_info(const void* h_header, uint64_t header_bytes, int* rank, uint64_t dims[3],
+                     ebc_params* p, int* codec, uint64_t* total_bytes)
+{
+    Header H;
+    int st = parse_header(h_header, header_bytes, &H);
+    if (st) return st;
+    if (rank) *rank = H.rank;
+    if (dims) memcpy(dims, H.dims, sizeof(H.dims));
+    if (p) {
+        p->eb_mode = H.eb_mode;
+        p->codec = EBC_CODEC_AUTO;
+        p->eb = H.eb;
+        p->n_bins = H.n_bins;
+        p->huff_chunk = H.hc;
+    }
+    if (codec) *codec = H.codec;
+    if (total_bytes) *total_bytes = H.total;
+    return EBC_OK;
+}
+
+int ebc_decompress_workspace_size(const void* h_header, uint64_t header_bytes, uint64_t* bytes)
+{
+    if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
+    std::vector<DecompressIn> din(1);
+    int st = parse_header(h_header, header_bytes, &din[0].H);
+    if (st) return st;
+    st = header_supported(din[0].H);
+    if (st) return st;
+    din[0].arc = nullptr, din[0].out = nullptr, din[0].size = din[0].H.total, din[0].out_elems = 0;
+    Batch B;
+    plan_decompress(B, din, nullptr);
+    *bytes = B.ws_bytes;
+    return EBC_OK;
+}
+
+static int decompress_impl(const Header& H, const void* d_archive, uint64_t size, float* d_out,
+                           uint64_t out_elems, void* d_ws, uint64_t ws_bytes, hipStream_t s,
+                           Batch& B, Timer& T)
+{
+    if (!d_archive || !d_out || !d_ws) return fail(EBC_ERR_ARG, "NULL argument");
+    int st = header_supported(H);
+    if (st) return st;
+    if (H.total > size) return fail(EBC_ERR_ARCHIVE, "archive truncated: %llu < %llu",
+                                    (unsigned long long)size, (unsigned long long)H.total);
+    if (out_elems < H.n) return fail(EBC_ERR_OUT_TOO_SMALL, "output holds %llu < %llu elements",
+                                     (unsigned long long)out_elems, (unsigned long long)H.n);
+    std::vector<DecompressIn> din(1);
+    din[0] = {H, d_archive, size, d_out, out_elems};
+    Batch sizing;
+    plan_decompress(sizing, din, nullptr);
+    if (ws_bytes < sizing.ws_bytes)
+        return fail(EBC_ERR_WS_TOO_SMALL, "workspace %llu < required %llu",
+                    (unsigned long long)ws_bytes, (unsigned long long)sizing.ws_bytes);
+    plan_decompress(B, din, (uint8_t*)d_ws);
+    return enqueue_decompress(B, s, T);
+}
+
+int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t out_elems,
+                   void* d_ws, uint64_t ws_bytes, void* stream, ebc_stats* stats)
+{
+    hipStream_t s = (hipStream_t)stream;
+    if (!d_archive) return fail(EBC_ERR_ARG, "archive is NULL");
+    if (size < kHdr) return fail(EBC_ERR_ARCHIVE, "archive shorter than its header");
+    uint8_t hdr[kHdr];
+    HIP_TRY(hipMemcpyAsync(hdr, d_archive, kHdr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    Header H;
+    int st = parse_header(hdr, kHdr, &H);
+    if (st) return st;
+    Batch B;
+    Timer T(stats, s);
+    st = decompress_impl(H, d_archive, size, d_out, out_elems, d_ws, ws_bytes, s, B, T);
+    if (st) return st;
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    T.finish();
+    if (stats) {
+        stats->codec = H.codec;
+        stats->n_elems = H.n;
+        stats->n_outliers = H.n_out;
+        stats->n_runs = H.codec == EBC_ARC_RLE ? H.n_a : 0;
+        stats->n_words = H.n_words;
+        stats->out_bytes = H.total;
+        stats->eb_abs = H.eb_abs;
+        stats->ebx2 = H.ebx2;
+    }
+    return status_of(dyn[0]);
+}
+
+int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t size, float* d_out,
+                         uint64_t out_elems, void* d_ws, uint64_t ws_bytes, int32_t* d_status,
+                         void* stream)
+{
+    if (!d_status) return fail(EBC_ERR_ARG, "d_status is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    Header H;
+    int st = parse_header(h_header, kHdr, &H);
+    if (st) return st;
+    Batch B;
+    Timer T(nullptr, s);
+    st = decompress_impl(H, d_archive, size, d_out, out_elems, d_ws, ws_bytes, s, B, T);
+    if (st) return st;
+    HIP_TRY(launch_status(B.d_fd, d_status, s));
+    return EBC_OK;
+}
+
+// ------------------------------------------------------------------ batch
+int ebc_batch_compress_workspace_size(int n, const ebc_field* fields, const ebc_params* p,
+                                      uint64_t* bytes)
+{
+    if (n <= 0 || !fields || !bytes) return fail(EBC_ERR_ARG, "bad batch arguments");
+    Params P;
+    int st = check_params(p, &P);
+    if (st) return st;
+    std::vector<CompressIn> fin(n);
+    for (int i = 0; i < n; ++i) {
+        uint64_t cnt;
+        st = check_dims(fields[i].rank, fields[i].dims, &cnt);
+        if (st) return st;
+        fin[i] = {fields[i].d_field, fields[i].rank,
+                  {fields[i].dims[0], fields[i].dims[1], fields[i].dims[2]}, fields[i].d_out,
+                  fields[i].out_cap};
+    }
+    Batch B;
+    plan_compress(B, fin, P, nullptr);
+    *bytes = B.ws_bytes;
+    return EBC_OK;
+}
+
+int ebc_batch_compress(int n, const ebc_field* fields, const ebc_params* p, ebc_result* results,
+                       void* d_ws, uint64_t ws_bytes, void* stream)
+{
+    if (n <= 0 || !fields || !results) return fail(EBC_ERR_ARG, "bad batch arguments");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(n);
+    for (int i = 0; i < n; ++i)
+        fin[i] = {fields[i].d_field, fields[i].rank,
+                  {fields[i].dims[0], fields[i].dims[1], fields[i].dims[2]}, fields[i].d_out,
+                  fields[i].out_cap};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(nullptr, s);
+    st = enqueue_compress(B, P, s, T);
+    if (st) return st;
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    int first_err = EBC_OK;
+    for (int k = 0; k < n; ++k) {
+        const int i = B.order[k];
+        results[i].status = dyn[k].status;
+        results[i].codec = dyn[k].codec;
+        results[i].out_size = dyn[k].status == ST_OK ? dyn[k].total : 0;
+        if (dyn[k].status != ST_OK && first_err == EBC_OK) first_err = status_of(dyn[k]);
+    }
+    return first_err;
+}
+
+static int batch_dec_inputs(int n, const ebc_archive_ref* refs, std::vector<DecompressIn>& din)
+{
+    if (n <= 0 || !refs) return fail(EBC_ERR_ARG, "bad batch arguments");
+    din.resize(n);
+    for (int i = 0; i < n; ++i) {
+        int st = parse_header(refs[i].h_header, kHdr, &din[i].H);
+        if (st) return st;
+        st = header_supported(din[i].H);
+        if (st) return st;
+        din[i].arc = refs[i].d_archive;
+        din[i].size = refs[i].size;
+        din[i].out = refs[i].d_out;
+        din[i].out_elems = refs[i].out_elems;
+    }
+    return EBC_OK;
+}
+
+int ebc_batch_decompress_workspace_size(int n, const ebc_archive_ref* refs, uint64_t* bytes)
+{
+    if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
+    std::vector<DecompressIn> din;
+    int st = batch_dec_inputs(n, refs, din);
+    if (st) return st;
+    Batch B;
+    plan_decompress(B, din, nullptr);
+    *bytes = B.ws_bytes;
+    return EBC_OK;
+}
+
+int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, void* d_ws,
+                         uint64_t ws_bytes, void* stream)
+{
+    if (!statuses || !d_ws) return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<DecompressIn> din;
+    int st = batch_dec_inputs(n, refs, din);
+    if (st) return st;
+    for (const auto& D : din) {
+        if (!D.arc || !D.out) return fail(EBC_ERR_ARG, "NULL archive or output");
+        if (D.H.total > D.size) return fail(EBC_ERR_ARCHIVE, "archive truncated");
+        if (D.out_elems < D.H.n) return fail(EBC_ERR_OUT_TOO_SMALL, "output too small");
+    }
+    Batch sizing;
+    plan_decompress(sizing, din, nullptr);
+    if (ws_bytes < sizing.ws_bytes) return fail(EBC_ERR_WS_TOO_SMALL, "workspace too small");
+    Batch B;
+    plan_decompress(B, din, (uint8_t*)d_ws);
+    Timer T(nullptr, s);
+    st = enqueue_decompress(B, s, T);
+    if (st) return st;
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    int first_err = EBC_OK;
+    for (int k = 0; k < n; ++k) {
+        statuses[B.order[k]] = dyn[k].status;
+        if (dyn[k].status != ST_OK && first_err == EBC_OK) first_err = status_of(dyn[k]);
+    }
+    return first_err;
+}
+
+// ------------------------------------------------------------------ debug
+int ebc_debug_construct(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+                        uint16_t* d_q, uint32_t* d_hist, uint32_t* d_oidx, int32_t* d_oval,
+                        uint64_t* n_outliers, double* ebx2, void* d_ws, uint64_t ws_bytes,
+                        void* stream)
+{
+    if (!d_q || !d_hist || !d_oidx || !d_oval || !n_outliers || !dims)
+        return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(1);
+    fin[0] = {d_field, rank, {dims[0], dims[1], dims[2]}, (void*)d_oidx, ~0ull};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(nullptr, s);
+    st = enqueue_compress(B, P, s, T, true);
+    if (st) return st;
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    st = status_of(dyn[0]);
+    if (st) return st;
+    const FieldDesc& d = B.fd[0];
+    if (dyn[0].codec == ARC_CONST) return fail(EBC_ERR_ARG, "constant field: nothing constructed");
+    // outlier count from the scanned segment counts, then compaction straight
+    // into the caller's arrays (the "archive" base is d_oidx)
+    uint32_t seg_tot[2];
+    HIP_TRY(hipMemcpyAsync(seg_tot, B.d_seg + d.seg_base + d.n_seg, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(seg_tot + 1, B.d_seg + d.seg_base, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    FieldDyn nd = dyn[0];
+    nd.n_out = seg_tot[0] - seg_tot[1];
+    nd.off_oidx = 0;
+    nd.off_oval = (uint64_t)((uintptr_t)d_oval - (uintptr_t)d_oidx);
+    HIP_TRY(hipMemcpyAsync(B.d_dyn, &nd, sizeof(FieldDyn), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_outlier_write(B.d_fd, 1, B.tot_ow, B.d_seg, s));
+    HIP_TRY(hipMemcpyAsync(d_q, d.q, 2 * d.n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_hist, d.hist, 4ull * P.n_bins, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *n_outliers = nd.n_out;
+    if (ebx2) *ebx2 = dyn[0].ebx2;
+    return EBC_OK;
+}
+
+int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int32_t* d_oval,
+                          uint64_t n_outliers, int rank, const uint64_t dims[3], uint32_t n_bins,
+                          double ebx2, float* d_out, void* d_ws, uint64_t ws_bytes, void* stream)
+{
+    if (!d_q || !d_out || !dims || !d_ws || (n_outliers && (!d_oidx || !d_oval)))
+        return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    Header H = {};
+    int st = check_dims(rank, dims, &H.n);
+    if (st) return st;
+    if (n_bins < 4 || n_bins > kMaxBins || (n_bins & 1)) return fail(EBC_ERR_BINS, "bad n_bins");
+    H.rank = rank;
+    memcpy(H.dims, dims, sizeof(H.dims));
+    H.codec = EBC_ARC_HUFFMAN;
+    H.n_bins = n_bins;
+    H.hc = 1024;
+    H.ebx2 = ebx2;
+    H.n_out = n_outliers;
+    H.off_oidx = 0;
+    const uintptr_t o_base = d_oidx ? (uintptr_t)d_oidx : (uintptr_t)d_q;
+    H.off_oval = (uint64_t)((d_oval ? (uintptr_t)d_oval : o_base) - o_base);
+    std::vector<DecompressIn> din(1);
+    din[0] = {H, (const void*)o_base, ~0ull, d_out, H.n};
+    Batch sizing;
+    plan_decompress(sizing, din, nullptr);
+    if (ws_bytes < sizing.ws_bytes) return fail(EBC_ERR_WS_TOO_SMALL, "workspace too small");
+    Batch B;
+    plan_decompress(B, din, (uint8_t*)d_ws);
+    FieldDesc& d = B.fd[0];
+    HIP_TRY(hipMemcpyAsync(d.q, d_q, 2 * H.n, hipMemcpyDeviceToDevice, s));
+    d.n_hch = 0, d.hdwg_units = 0;  // no entropy decoding
+    HIP_TRY(upload_descs(B.fd.data(), 1, B.d_fd, s));
+    HIP_TRY(launch_dinit(B.d_fd, 1, s));
+    HIP_TRY(launch_outlier_scatter(B.d_fd, 1, B.tot_sc, s));
+    for (const auto& G : B.groups)
+        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, s));
+    HIP_TRY(launch_recon_check(B.d_fd, 1, s));
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    return status_of(dyn[0]);
+}
+
+}  // extern "C"

@@ -1,0 +1,121 @@
+// k_outlier.hip -- ordered outlier list: compaction at compression, scatter
+// at decompression.
+//
+// Sec. IV-B.1 (modified quantisation): an out-of-range delta keeps its code
+// slot as the placeholder 0 and is stored exactly in a separate list; before
+// reconstruction the list is fused back (Algorithm 1, decompression half).
+// The list is ordered by linear index.  Compression already counted the
+// outliers of every row segment (the x-extent of one construct wave-tile);
+// after a scan of those counts, each segment with outliers is compacted by
+// one wavefront with ballot ranks.  Decompression scatters the list into a
+// dense delta scratch and validates it against the codes.
+#include "ebc_dev.h"
+#include "ebc_launch.h"
+
+namespace ebc {
+
+constexpr uint32_t kSegPerWave = 256;
+constexpr uint32_t kSegPerBlock = kSegPerWave * kWavesPerBlock;
+
+uint32_t outlier_write_units(uint32_t n_seg) { return (n_seg + kSegPerBlock - 1) / kSegPerBlock; }
+
+// element range [a, b) of segment s
+__device__ __forceinline__ void seg_range(const FieldDesc& fd, uint32_t s, uint64_t& a, uint64_t& b)
+{
+    if (fd.rank == 1) {
+        a = (uint64_t)s * 256;
+        b = min(a + 256, fd.n);
+    } else {
+        const uint32_t xs = 4 * fd.lx;
+        const uint64_t row = s / fd.nxb;
+        const uint32_t xb = s % fd.nxb;
+        a = row * fd.nx + (uint64_t)xb * xs;
+        b = row * fd.nx + min((uint64_t)(xb + 1) * xs, (uint64_t)fd.nx);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_outlier_write(const FieldDesc* __restrict__ F, int nf,
+                                                          const uint32_t* __restrict__ soff)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::ow_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec == ARC_CONST || dy->n_out == 0) return;
+    const int l = lane_id();
+    const uint32_t* off = soff + fd.seg_base;
+    const uint32_t off0 = off[0];
+    uint32_t* oidx = (uint32_t*)(fd.arc + dy->off_oidx);
+    int32_t* oval = (int32_t*)(fd.arc + dy->off_oval);
+    const uint32_t s_lo = (t - fd.ow_base) * kSegPerBlock + (threadIdx.x / kWave) * kSegPerWave;
+    for (uint32_t sb = s_lo; sb < s_lo + kSegPerWave && sb < fd.n_seg; sb += kWave) {
+        const uint32_t s = sb + l;
+        const bool ok = s < fd.n_seg;
+        const uint32_t o0 = ok ? off[s] : 0u, o1 = ok ? off[s + 1] : 0u;
+        uint64_t todo = ballot(ok && o1 != o0);
+        while (todo) {
+            const int j = __ffsll((long long)todo) - 1;
+            todo &= todo - 1;
+            const uint32_t seg = sb + j;
+            const uint32_t base = __shfl(o0, j) - off0;
+            uint64_t a, b;
+            seg_range(fd, seg, a, b);
+            // a segment spans at most 256 elements: 4 per lane
+            uint32_t zm = 0;
+            const uint64_t e0 = a + 4 * (uint64_t)l;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (e0 + k < b && fd.q[e0 + k] == 0) zm |= 1u << k;
+            const uint32_t mine = __popc(zm);
+            uint32_t pos = base + wave_incl_scan_u32(mine) - mine;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (zm & (1u << k)) {
+                    oidx[pos] = (uint32_t)(e0 + k);
+                    oval[pos] = fd.dsc[e0 + k];
+                    ++pos;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------- decoding
+// one thread per listed outlier: index in range, strictly ascending, code 0
+__global__ __launch_bounds__(kBlock) void k_outlier_scatter(const FieldDesc* __restrict__ F, int nf)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::sc_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || fd.codec_hdr == ARC_CONST) return;
+    const uint64_t k = (uint64_t)(t - fd.sc_base) * kBlock + threadIdx.x;
+    if (k >= fd.n_out_hdr) return;
+    const uint32_t* oidx = (const uint32_t*)(fd.arc + fd.off_oidx);
+    const int32_t* oval = (const int32_t*)(fd.arc + fd.off_oval);
+    const uint32_t i = oidx[k];
+    bool bad = i >= fd.n || (k > 0 && oidx[k - 1] >= i);
+    if (!bad) bad = fd.q[i] != 0;
+    if (bad) {
+        atomicMin(&dy->status, ST_ERR_ARCHIVE);
+        return;
+    }
+    fd.dsc[i] = oval[k];
+}
+
+hipError_t launch_outlier_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* soff,
+                                hipStream_t s)
+{
+    if (!units) return hipSuccess;
+    hipLaunchKernelGGL(k_outlier_write, dim3(units), dim3(kBlock), 0, s, F, nf, soff);
+    return hipGetLastError();
+}
+
+hipError_t launch_outlier_scatter(const FieldDesc* F, int nf, uint32_t units, hipStream_t s)
+{
+    if (!units) return hipSuccess;
+    hipLaunchKernelGGL(k_outlier_scatter, dim3(units), dim3(kBlock), 0, s, F, nf);
+    return hipGetLastError();
+}
+
+}  // namespace ebc

@@ -1,0 +1,262 @@
+// k_rle.hip -- run-length encoding of the quant-codes and its inverse.
+//
+// Sec. III-B: a run of equal symbols is stored as a (value, count) tuple; the
+// run lengths are metadata.  Runs are maximal and taken over the whole code
+// array in row-major order.  Encoding marks run starts (a code differing from
+// its predecessor), counts them per tile, scans the counts, and compacts
+// (value, start) pairs in order; lengths are differences of successive
+// starts.  Decoding scans the stored lengths into starts and expands each
+// output tile from the runs that overlap it.
+#include "ebc_dev.h"
+#include "ebc_launch.h"
+
+namespace ebc {
+
+constexpr int kRleItems = kRleTile / kBlock;  // 16 codes per thread
+
+// load 16 codes owned by this thread and the flags "starts a run"
+__device__ __forceinline__ uint32_t run_flags(const FieldDesc& fd, uint64_t lo, uint16_t c[kRleItems])
+{
+    __shared__ uint16_t s_last[kBlock];
+    const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
+    const uint64_t n = fd.n;
+    const uint16_t* __restrict__ q = fd.q;
+    if (i0 + kRleItems <= n) {
+        const uint4 a = *(const uint4*)(q + i0);
+        const uint4 b = *(const uint4*)(q + i0 + 8);
+        const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c[2 * k] = w[k] & 0xFFFF, c[2 * k + 1] = w[k] >> 16;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kRleItems; ++k) c[k] = i0 + k < n ? q[i0 + k] : 0;
+    }
+    s_last[threadIdx.x] = c[kRleItems - 1];
+    __syncthreads();
+    uint32_t prev;
+    bool have_prev;
+    if (threadIdx.x > 0) {
+        prev = s_last[threadIdx.x - 1];
+        have_prev = true;
+    } else {
+        have_prev = lo > 0;
+        prev = have_prev ? q[lo - 1] : 0u;
+    }
+    uint32_t flags = 0;
+#pragma unroll
+    for (int k = 0; k < kRleItems; ++k) {
+        if (i0 + k < n && (!have_prev || c[k] != prev)) flags |= 1u << k;
+        prev = c[k];
+        have_prev = true;
+    }
+    __syncthreads();
+    return flags;
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_rle(uint32_t v, uint32_t* total)
+{
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    const int w = threadIdx.x / kWave;
+    const uint32_t inc = wave_incl_scan_u32(v);
+    if (lane_id() == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; ++k) {
+        off += k < w ? s_w[k] : 0u;
+        tot += s_w[k];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restrict__ F, int nf,
+                                                      uint32_t* __restrict__ rcnt)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
+    uint16_t c[kRleItems];
+    const uint32_t flags = run_flags(fd, (uint64_t)(t - fd.rt_base) * kRleTile, c);
+    uint32_t tot;
+    block_excl_scan_rle(__popc(flags), &tot);
+    if (threadIdx.x == 0) rcnt[t] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restrict__ F, int nf,
+                                                      const uint32_t* __restrict__ roff)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
+    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    uint16_t c[kRleItems];
+    const uint32_t flags = run_flags(fd, lo, c);
+    uint32_t tot;
+    uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
+    uint16_t* val = (uint16_t*)(fd.arc + kHdr);
+    const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
+#pragma unroll
+    for (int k = 0; k < kRleItems; ++k) {
+        if (flags & (1u << k)) {
+            val[pos] = c[k];
+            fd.rstart[pos] = (uint32_t)(i0 + k);
+            ++pos;
+        }
+    }
+}
+
+// lengths = differences of successive starts; grid-stride over the runs
+__global__ __launch_bounds__(kBlock) void k_rle_len(const FieldDesc* __restrict__ F)
+{
+    const FieldDesc& fd = F[blockIdx.y];
+    const FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
+    const uint64_t R = dy->n_runs;
+    uint32_t* len = (uint32_t*)(fd.arc + dy->off_rlen);
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < R;
+         k += (uint64_t)gridDim.x * kBlock) {
+        const uint64_t end = k + 1 < R ? fd.rstart[k + 1] : fd.n;
+        len[k] = (uint32_t)(end - fd.rstart[k]);
+    }
+}
+
+// ------------------------------------------------------------- decoding
+// run lengths from the archive into the batch-wide array; zero-length runs
+// are malformed
+__global__ __launch_bounds__(kBlock) void k_rle_prep(const FieldDesc* __restrict__ F, int nf,
+                                                     uint32_t* __restrict__ starts)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::rl_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
+    if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
+    const uint32_t L = ((const uint32_t*)(fd.arc + fd.off_rlen))[k];
+    if (L == 0) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
+    starts[fd.rle_base + k] = L;
+}
+
+// runs must cover the field exactly
+__global__ void k_rle_check(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ starts)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const FieldDesc& fd = F[f];
+    if (fd.codec_hdr != ARC_RLE) return;
+    const uint32_t total = starts[fd.rle_base + fd.n_runs_hdr] - starts[fd.rle_base];
+    if ((uint64_t)total != fd.n) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
+}
+
+__global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restrict__ F, int nf,
+                                                       const uint32_t* __restrict__ starts)
+{
+    __shared__ uint32_t s_start[kRleTile + 1];
+    __shared__ uint16_t s_val[kRleTile + 1];
+    __shared__ uint32_t s_rlo, s_nr;
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || fd.codec_hdr != ARC_RLE) return;
+    const uint32_t* S = starts + fd.rle_base;
+    const uint32_t s0 = S[0];
+    const uint32_t R = fd.n_runs_hdr;
+    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    const uint64_t hi = min(lo + (uint64_t)kRleTile, fd.n);
+    if (threadIdx.x == 0) {
+        // largest r with start[r] <= lo, and largest r with start[r] <= hi - 1
+        uint32_t a = 0, b = R - 1;
+        while (a < b) {
+            const uint32_t m = (a + b + 1) >> 1;
+            if ((uint64_t)(S[m] - s0) <= lo) a = m;
+            else b = m - 1;
+        }
+        uint32_t c = a, d = R - 1;
+        while (c < d) {
+            const uint32_t m = (c + d + 1) >> 1;
+            if ((uint64_t)(S[m] - s0) <= hi - 1) c = m;
+            else d = m - 1;
+        }
+        s_rlo = a;
+        s_nr = c - a + 1;
+    }
+    __syncthreads();
+    const uint32_t rlo = s_rlo, nr = s_nr;  // nr <= kRleTile because every run is non-empty
+    const uint16_t* val = (const uint16_t*)(fd.arc + fd.off_val);
+    for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
+        s_start[i] = S[rlo + i] - s0;
+        s_val[i] = val[rlo + i];
+    }
+    __syncthreads();
+    const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
+    if (i0 >= hi) return;
+    // run of the first owned element, then walk forward
+    uint32_t a = 0, b = nr - 1;
+    while (a < b) {
+        const uint32_t m = (a + b + 1) >> 1;
+        if ((uint64_t)s_start[m] <= i0) a = m;
+        else b = m - 1;
+    }
+    uint16_t c[kRleItems];
+#pragma unroll
+    for (int k = 0; k < kRleItems; ++k) {
+        const uint64_t i = i0 + k;
+        while (a + 1 < nr && (uint64_t)s_start[a + 1] <= i) ++a;
+        c[k] = s_val[a];
+    }
+    uint16_t* __restrict__ q = fd.q;
+    if (i0 + kRleItems <= hi) {
+        uint4 x, y;
+        x.x = c[0] | ((uint32_t)c[1] << 16), x.y = c[2] | ((uint32_t)c[3] << 16);
+        x.z = c[4] | ((uint32_t)c[5] << 16), x.w = c[6] | ((uint32_t)c[7] << 16);
+        y.x = c[8] | ((uint32_t)c[9] << 16), y.y = c[10] | ((uint32_t)c[11] << 16);
+        y.z = c[12] | ((uint32_t)c[13] << 16), y.w = c[14] | ((uint32_t)c[15] << 16);
+        *(uint4*)(q + i0) = x;
+        *(uint4*)(q + i0 + 8) = y;
+    } else {
+        for (int k = 0; k < kRleItems; ++k)
+            if (i0 + k < hi) q[i0 + k] = c[k];
+    }
+}
+
+hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t* rcnt, hipStream_t s)
+{
+    if (!units) return hipSuccess;
+    hipLaunchKernelGGL(k_rle_count, dim3(units), dim3(kBlock), 0, s, F, nf, rcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff,
+                            hipStream_t s)
+{
+    if (!units) return hipSuccess;
+    hipLaunchKernelGGL(k_rle_write, dim3(units), dim3(kBlock), 0, s, F, nf, roff);
+    return hipGetLastError();
+}
+
+hipError_t launch_rle_len(const FieldDesc* F, int nf, uint32_t max_units, hipStream_t s)
+{
+    const uint32_t g = max(1u, min(max_units, 2048u));
+    hipLaunchKernelGGL(k_rle_len, dim3(g, nf), dim3(kBlock), 0, s, F);
+    return hipGetLastError();
+}
+
+hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint32_t rt_units,
+                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, hipStream_t s)
+{
+    if (!rl_units) return hipSuccess;
+    hipLaunchKernelGGL(k_rle_prep, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
+    hipError_t e = launch_scan(starts, n_starts, tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rle_check, dim3((nf + 63) / 64), dim3(64), 0, s, F, nf, starts);
+    if (rt_units) hipLaunchKernelGGL(k_rle_expand, dim3(rt_units), dim3(kBlock), 0, s, F, nf, starts);
+    return hipGetLastError();
+}
+
+}  // namespace ebc

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Everything after prequantisation is integer, so the bar is bit-exact:
+identical quant-codes, histogram, ordered outlier list, archive bytes and
+reconstructed floats (compared as bit patterns).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_12912_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2105_12912_amd import ebc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ebc.lib()
+    return ebc
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+def rng_field(shape, seed, kind="grf"):
+    if kind == "noise":
+        return np.random.default_rng(seed).standard_normal(shape).astype(np.float32)
+    if kind == "lognormal":
+        return synth.lognormal_3d(shape, seed) if len(shape) == 3 else np.exp(
+            1.5 * synth.grf(shape, -3.0, seed)).astype(np.float32)
+    if kind == "walk":
+        return synth.random_walk_1d(shape[0], seed)
+    return synth.grf_field(shape, seed)
+
+
+CASES = [
+    # name, shape, kind, eb, mode, n_bins
+    ("smooth256", (256, 256), "grf", 1e-4, "rel", 1024),
+    ("2d_ragged", (37, 53), "grf", 1e-4, "rel", 1024),
+    ("2d_narrow", (300, 6), "grf", 1e-3, "rel", 1024),
+    ("2d_noise", (70, 90), "noise", 1e-4, "rel", 1024),
+    ("1d_walk", (50000,), "walk", 1e-4, "rel", 1024),
+    ("1d_ragged", (1000003,), "walk", 1e-3, "rel", 256),
+    ("1d_tiny", (7,), "noise", 1e-2, "rel", 1024),
+    ("3d_grf", (40, 48, 64), "grf", 1e-4, "rel", 1024),
+    ("3d_ragged", (9, 10, 11), "grf", 1e-3, "rel", 1024),
+    ("3d_lognormal", (24, 40, 33), "lognormal", 1e-3, "rel", 1024),
+    ("3d_abs", (20, 17, 30), "grf", 1e-3, "abs", 1024),
+    ("3d_wide", (16, 8, 600), "grf", 1e-4, "rel", 1024),
+    ("bins4", (64, 64), "grf", 1e-3, "rel", 4),
+    ("bins4096", (64, 80), "noise", 1e-4, "rel", 4096),
+    ("bins64", (33, 65, 17), "noise", 1e-3, "rel", 64),
+]
+
+
+@pytest.mark.parametrize("name,shape,kind,eb,mode,nb", CASES, ids=[c[0] for c in CASES])
+def test_construct_intermediates(E, name, shape, kind, eb, mode, nb):
+    x = rng_field(shape, 11, kind)
+    it = O.intermediates(x, eb, mode, n_bins=nb)
+    g = E.debug_construct(dev(x), eb, mode, n_bins=nb)
+    assert g["ebx2"] == it["ebx2"]
+    np.testing.assert_array_equal(g["q"].cpu().numpy().view(np.uint16), it["q"].ravel())
+    np.testing.assert_array_equal(g["hist"].cpu().numpy().astype(np.uint64), it["hist"])
+    np.testing.assert_array_equal(g["oidx"].cpu().numpy().view(np.uint32), it["oidx"])
+    np.testing.assert_array_equal(g["oval"].cpu().numpy(), it["oval"])
+
+
+@pytest.mark.parametrize("name,shape,kind,eb,mode,nb", CASES, ids=[c[0] for c in CASES])
+def test_archive_bytes_and_roundtrip(E, name, shape, kind, eb, mode, nb):
+    x = rng_field(shape, 12, kind)
+    ref = O.compress(x, eb, mode, n_bins=nb)
+    a = E.compress(dev(x), eb, mode, n_bins=nb)
+    got = a.cpu().numpy().tobytes()
+    assert len(got) == len(ref)
+    assert got == ref
+    y = E.decompress(a)
+    yo = O.decompress(ref)
+    np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(yo))
+    rng = float(x.max()) - float(x.min())
+    eb_abs = eb * rng if mode == "rel" else eb
+    assert float(np.max(np.abs(y.cpu().numpy().astype(np.float64) - x))) <= eb_abs
+
+
+@pytest.mark.parametrize("codec", ["huffman", "rle"])
+@pytest.mark.parametrize("shape", [(256, 256), (9, 10, 11), (5000,)])
+def test_forced_codecs(E, codec, shape):
+    x = rng_field(shape, 13)
+    ref = O.compress(x, 1e-3, codec=codec)
+    a = E.compress(dev(x), 1e-3, codec=codec)
+    assert a.cpu().numpy().tobytes() == ref
+    np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
+
+
+@pytest.mark.parametrize("hc", [64, 256, 2048, 4096])
+def test_huffman_chunk_sizes(E, hc):
+    x = rng_field((70, 90), 14, "noise")
+    ref = O.compress(x, 1e-4, codec="huffman", hc=hc)
+    a = E.compress(dev(x), 1e-4, codec="huffman", huff_chunk=hc)
+    assert a.cpu().numpy().tobytes() == ref
+    np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
+
+
+def test_constant_field(E):
+    x = np.full((33, 45), -2.5, np.float32)
+    a = E.compress(dev(x), 1e-4)
+    assert a.cpu().numpy().tobytes() == O.compress(x, 1e-4)
+    np.testing.assert_array_equal(E.decompress(a).cpu().numpy(), x)
+
+
+def test_constant_field_abs(E):
+    x = np.full((3, 5, 7), 0.25, np.float32)
+    a = E.compress(dev(x), 1e-3, "abs")
+    assert a.cpu().numpy().tobytes() == O.compress(x, 1e-3, "abs")
+
+
+def test_signed_zero_and_single(E):
+    x = np.array([0.0, -0.0, 0.0], np.float32)
+    assert E.compress(dev(x), 1e-3).cpu().numpy().tobytes() == O.compress(x, 1e-3)
+    x1 = np.array([1.5], np.float32)
+    assert E.compress(dev(x1), 1e-3, "abs").cpu().numpy().tobytes() == O.compress(x1, 1e-3, "abs")
+    x3 = np.array([[[2.0]]], np.float32)
+    assert E.compress(dev(x3), 1e-3, "abs").cpu().numpy().tobytes() == O.compress(x3, 1e-3, "abs")
+
+
+def test_denormal_and_huge_eb(E):
+    x = (np.random.default_rng(3).standard_normal((40, 40)) * 1e-39).astype(np.float32)
+    assert E.compress(dev(x), 1e-2).cpu().numpy().tobytes() == O.compress(x, 1e-2)
+    y = rng_field((32, 32), 4)
+    assert E.compress(dev(y), 10.0, "abs").cpu().numpy().tobytes() == O.compress(y, 10.0, "abs")
+
+
+def test_reconstruct_alone_matches_oracle(E):
+    """Reconstruction from oracle-made codes and outliers (partial sum vs recurrence)."""
+    for shape in [(257,), (37, 53), (17, 9, 20), (8, 8, 600)]:
+        x = rng_field(shape, 15, "noise")
+        it = O.intermediates(x, 1e-4, n_bins=64)
+        qp = O.fuse(it["q"], 64, it["oidx"], it["oval"])
+        want = O.dequant(O.reconstruct(qp, len(shape)), it["ebx2"])
+        out = E.debug_reconstruct(dev(it["q"].view(np.int16).ravel()), dev(it["oidx"].view(np.int32)),
+                                  dev(it["oval"]), len(shape), shape[::-1], 64, it["ebx2"])
+        np.testing.assert_array_equal(bits(out.cpu().numpy()), bits(want.ravel()))
+
+
+def test_error_paths(E):
+    x = rng_field((16, 16), 5)
+    y = x.copy()
+    y[3, 4] = np.nan
+    with pytest.raises(E.EbcError) as ei:
+        E.compress(dev(y), 1e-3)
+    assert ei.value.status == E.EBC_ERR_NONFINITE
+    y[3, 4] = np.inf
+    with pytest.raises(E.EbcError) as ei:
+        E.compress(dev(y), 1e-3)
+    assert ei.value.status == E.EBC_ERR_NONFINITE
+    with pytest.raises(E.EbcError) as ei:
+        E.compress(dev(x * 1e6), 1e-12, "abs")
+    assert ei.value.status == E.EBC_ERR_EB_TOO_SMALL
+    assert O.compress_status(x * 1e6, 1e-12, "abs") == E.EBC_ERR_EB_TOO_SMALL
+    # output buffer too small: detected on the device, reported after the sync
+    xt = dev(x)
+    out = torch.empty(200, dtype=torch.uint8, device="cuda")
+    p = E.make_params(1e-4)
+    ws = E.default_workspace()
+    wptr, wlen = ws.get(E.ebc_compress_workspace_size(2, (16, 16), p))
+    st, size = E.ebc_compress(xt.data_ptr(), 2, (16, 16), p, out.data_ptr(), out.numel(), wptr,
+                              wlen, E._stream_handle(None))
+    assert st == E.EBC_ERR_OUT_TOO_SMALL and size == 0
+    st, _ = E.ebc_compress(xt.data_ptr(), 2, (16, 16), p, out.data_ptr(), out.numel(), wptr, 16,
+                           E._stream_handle(None))
+    assert st == E.EBC_ERR_WS_TOO_SMALL
+
+
+def test_corrupt_archives_rejected(E):
+    x = rng_field((64, 64), 6, "noise")
+    a = E.compress(dev(x), 1e-4)
+    raw = a.cpu().numpy().copy()
+    for mutate in ("magic", "truncate", "bits", "outlier"):
+        b = raw.copy()
+        if mutate == "magic":
+            b[0] = ord("X")
+        elif mutate == "truncate":
+            b = b[:-16]
+        elif mutate == "bits":
+            info = O.archive_info(raw.tobytes())
+            ob = (128 + info["n_bins"] + 15) & ~15
+            b[ob:ob + 4] = np.frombuffer(np.uint32(7).tobytes(), np.uint8)
+        else:
+            s = O.sections(raw.tobytes())
+            if s["info"]["n_outliers"] == 0:
+                continue
+            info = s["info"]
+            # point the first outlier at a non-placeholder code
+            nch, nw = info["n_a"], info["n_words"]
+            ob = (128 + info["n_bins"] + 15) & ~15
+            ow = (ob + 4 * nch + 15) & ~15
+            oo = (ow + 4 * nw + 15) & ~15
+            it = O.intermediates(x, 1e-4)
+            nz = int(np.flatnonzero(it["q"].ravel() != 0)[0])
+            b[oo:oo + 4] = np.frombuffer(np.uint32(nz).tobytes(), np.uint8)
+        st_o = O.decompress_status(b.tobytes())
+        st_g = E.decompress_status(dev(b))
+        assert st_o == -9, mutate
+        assert st_g == E.EBC_ERR_ARCHIVE, mutate
+
+
+def test_full_size_2d_bytes(E):
+    """1800 x 3600 (CESM-ATM shape): whole archive equal at rel 1e-4 and 1e-3."""
+    x = synth.climate_2d()
+    xd = dev(x)
+    for eb in (1e-4, 1e-3):
+        ref = O.compress(x, eb)
+        a = E.compress(xd, eb)
+        assert a.cpu().numpy().tobytes() == ref
+        y = E.decompress(a)
+        np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(O.decompress(ref)))

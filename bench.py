@@ -1,0 +1,250 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the compressor hot path on one MI355X.
+
+One step = compress + decompress of the 512^3 fp32 cosmology-like field
+(lognormal density, sigma 1.5, 40 % constant background; the Nyx shape of the
+paper's dataset table) at a value-range-relative error bound of 1e-4 with 1024
+quantisation bins, through the C ABI (plain path: each call synchronises once
+to return its size / status).  Inputs are resident in HBM before timing.
+
+Prints one JSON line with the round-trip throughput (input GB/s), the
+compress and decompress rates, per-kernel times from HIP events recorded on
+the launch stream, the roofline of the dominant kernel, and the CPU oracle
+timed on the host (single thread) on the same field.
+
+  python bench.py [--steps K] [--warmup W] [--workload nyx512|cesm2d|...]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+
+WORKLOADS = {
+    # name: (description, generator, rank shape, rel eb)
+    "nyx512": ("lognormal 3D 512x512x512 fp32, 40% constant background, rel eb 1e-4, 1024 bins",
+               lambda s: s.lognormal_3d((512, 512, 512), 3), 1e-4),
+    "nyx512_1e-3": ("lognormal 3D 512x512x512 fp32, 40% constant background, rel eb 1e-3, 1024 bins",
+                    lambda s: s.lognormal_3d((512, 512, 512), 3), 1e-3),
+    "cesm2d": ("GRF 2D 1800x3600 fp32 + 1e-5 white noise, rel eb 1e-4, 1024 bins",
+               lambda s: s.climate_2d(), 1e-4),
+    "smooth256": ("GRF 2D 256x256 fp32, rel eb 1e-4, 1024 bins",
+                  lambda s: s.smooth_2d(256, 256, 1), 1e-4),
+}
+
+# kernel stage -> algorithmic bytes per launch (n elements, o outliers, w words, r runs)
+def algo_bytes(stage: str, n: int, o: int, w: int, r: int, n_bins: int) -> float | None:
+    table = {
+        "range": 4 * n,
+        "construct": 4 * n + 2 * n + 8 * o,
+        "encode_count": 2 * n,
+        "encode_write": 2 * n + 4 * w,
+        "outlier_write": 8 * o,
+        "huffman_decode": 4 * w + 2 * n,
+        "rle_decode": 6 * r + 2 * n,
+        "outlier_scatter": 12 * o,
+        "reconstruct": 2 * n + 4 * o + 4 * n,
+    }
+    return table.get(stage)
+
+
+def kernel_source_hash(paths) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "construct": ["paper_2105_12912_amd/csrc/k_quant.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
+    "reconstruct": ["paper_2105_12912_amd/csrc/k_recon.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
+    "huffman_decode": ["paper_2105_12912_amd/csrc/k_huffman.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
+    "encode_write": ["paper_2105_12912_amd/csrc/k_huffman.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
+}
+
+
+def traffic_from_profiles(kernel: str, workload: str):
+    """HBM bytes per launch from a committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+        return None
+    try:
+        rec = json.load(open(path)).get(f"{kernel}/{workload}")
+    except Exception:
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(x: np.ndarray, eb: float, ref_bytes: bytes | None):
+    from oracle import oracle as O
+
+    t0 = time.perf_counter()
+    a = O.compress(x, eb, "rel")
+    t1 = time.perf_counter()
+    y = O.decompress(a)
+    t2 = time.perf_counter()
+    gb = x.nbytes / 1e9
+    return dict(
+        value=round(gb / (t2 - t0), 4), unit="GB/s", cores=1, kind="oracle",
+        sample=f"whole field once ({x.size} elements): compress {t1 - t0:.2f}s + decompress {t2 - t1:.2f}s, single thread",
+        compress_GBps=round(gb / (t1 - t0), 4), decompress_GBps=round(gb / (t2 - t1), 4),
+    ), a, y
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="nyx512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the compressor path "
+                                   "shards by independent chunks but no multi-GPU run is built; "
+                                   "use --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2105_12912_amd import ebc, synth
+
+    desc, gen, eb = WORKLOADS[args.workload]
+    print(f"[bench] generating {args.workload}: {desc}", file=sys.stderr, flush=True)
+    x = gen(synth)
+    n = x.size
+    dev = torch.device("cuda:0")
+    xd = torch.from_numpy(x).to(dev)
+    torch.cuda.synchronize()
+    ws = ebc.Workspace(dev)
+    out_buf = None
+
+    def step(timing: bool):
+        nonlocal out_buf
+        a, cs = ebc.compress(xd, eb, "rel", stats=True, workspace=ws, out=out_buf) if timing else \
+            (ebc.compress(xd, eb, "rel", workspace=ws, out=out_buf), None)
+        if out_buf is None:
+            out_buf = torch.empty(ebc.ebc_compress_bound(xd.dim(), tuple(reversed(xd.shape)),
+                                                         ebc.make_params(eb)),
+                                  dtype=torch.uint8, device=dev)
+        y, ds = ebc.decompress(a, out=ydev, stats=True, workspace=ws) if timing else \
+            (ebc.decompress(a, out=ydev, workspace=ws), None)
+        return a, y, cs, ds
+
+    ydev = torch.empty_like(xd)
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(max(args.warmup, 1)):
+        a, y, _, _ = step(False)
+    torch.cuda.synchronize()
+
+    timing = not args.no_timing
+    stage_sum: dict[str, float] = {}
+    comp_ms = dec_ms = 0.0
+    s = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    ev0.record(s)
+    last_cs = last_ds = None
+    for _ in range(args.steps):
+        a, y, cs, ds = step(timing)
+        if timing:
+            for k, v in cs.stages().items():
+                stage_sum["c:" + k] = stage_sum.get("c:" + k, 0.0) + v
+            for k, v in ds.stages().items():
+                stage_sum["d:" + k] = stage_sum.get("d:" + k, 0.0) + v
+            last_cs, last_ds = cs, ds
+    ev1.record(s)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    gb = x.nbytes / 1e9
+
+    # separate untimed passes for the compress-only and decompress-only rates
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = max(3, min(args.steps, 10))
+    e0.record(s)
+    for _ in range(reps):
+        a = ebc.compress(xd, eb, "rel", workspace=ws, out=out_buf)
+    e1.record(s)
+    for _ in range(reps):
+        y = ebc.decompress(a, out=ydev, workspace=ws)
+    e2.record(s)
+    torch.cuda.synchronize()
+    comp_ms = e0.elapsed_time(e1) / reps
+    dec_ms = e1.elapsed_time(e2) / reps
+
+    # correctness of what was timed: error bound on every element
+    rng = float(x.max()) - float(x.min())
+    err = float((y.double() - xd.double()).abs().max())
+    ok_bound = err <= eb * rng
+    arc = a.cpu().numpy().tobytes()
+    info = ebc.ebc_archive_info(arc[:128])
+
+    result = {
+        "metric": "Compress & decompress GB/s at rel eb 1e-4, % of HBM peak; batched vs plain",
+        "value": round(gb / (ms / 1e3), 3),
+        "unit": "GB/s (input bytes per compress+decompress round trip)",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 in / f64 quantisation / int32 codes",
+        "data": "synthetic (seeded GRF-based field, numpy default_rng)",
+        "config": {"workload": args.workload, "description": desc, "elements": n,
+                   "input_bytes": x.nbytes, "eb_rel": eb, "n_bins": 1024, "huff_chunk": 1024,
+                   "path": "plain (one field per call)"},
+        "compress_GBps": round(gb / (comp_ms / 1e3), 3),
+        "decompress_GBps": round(gb / (dec_ms / 1e3), 3),
+        "compress_ms": round(comp_ms, 4), "decompress_ms": round(dec_ms, 4),
+        "archive_bytes": len(arc), "compression_ratio": round(x.nbytes / len(arc), 3),
+        "codec": ["huffman", "rle", "const"][info["codec"]],
+        "max_abs_err": err, "error_bound_ok": ok_bound,
+    }
+    if timing and last_cs is not None:
+        stages = {k: round(v / args.steps, 5) for k, v in stage_sum.items()}
+        result["stage_ms"] = stages
+        o, w, r = last_cs.n_outliers, last_cs.n_words, last_cs.n_runs
+        roof = {}
+        for key, t in stages.items():
+            name = key.split(":", 1)[1]
+            b = algo_bytes(name, n, o, w, r, 1024)
+            if b is None or t <= 0:
+                continue
+            ach = b / (t / 1e3) / 1e9
+            roof[name] = dict(ms=t, algo_bytes=int(b), GBps=round(ach, 1),
+                              frac=round(ach / HBM_PEAK_GBPS, 4))
+        result["kernel_roofline"] = roof
+        dom = max(roof, key=lambda k: roof[k]["ms"]) if roof else None
+        if dom:
+            tb = traffic_from_profiles(dom, args.workload)
+            result["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": roof[dom]["GBps"],
+                                  "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": roof[dom]["frac"],
+                                  "traffic": tb}
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        cb, oarc, oy = cpu_baseline(x, eb, arc)
+        result["cpu_baseline"] = cb
+        result["parity_vs_oracle"] = {
+            "archive_bytes_equal": oarc == arc,
+            "reconstruction_bits_equal": bool(np.array_equal(oy.view(np.uint32),
+                                                             y.cpu().numpy().view(np.uint32))),
+        }
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

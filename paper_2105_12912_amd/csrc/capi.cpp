@@ -1,4 +1,4 @@
-// capi.hip -- C ABI of the compressor: validation, planning, workspace
+// capi.cpp -- C ABI of the compressor: validation, planning, workspace
 // carving and the kernel sequences for compression and decompression.
 //
 // Every call is a batch: fields are grouped by (rank, 16-byte row alignment)
@@ -17,7 +17,7 @@
 #include <vector>
 
 #include "../../include/ebc.h"
-#include "ebc_dev.h"
+#include "ebc_types.h"
 #include "ebc_launch.h"
 
 using namespace ebc;
@@ -307,8 +307,7 @@ struct Timer {
     // call after the stream has been synchronised
     void finish()
     {
-        if (!on) return;
-        mark("end");
+        if (!on || ev.empty()) return;
         (void)hipEventSynchronize(ev.back());
         st->n_stages = 0;
         for (size_t k = 0; k + 1 < ev.size(); ++k) {
@@ -573,16 +572,6 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
     B.ws_bytes = bp.off;
 }
 
-__global__ void k_words_check(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ woff)
-{
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    const FieldDesc& fd = F[f];
-    if (fd.codec_hdr != ARC_HUFFMAN) return;
-    const uint32_t tot = woff[fd.hch_base + fd.n_hch] - woff[fd.hch_base];
-    if ((uint64_t)tot != fd.n_words_hdr) atomicMin(&fd.dyn->status, (int32_t)ST_ERR_ARCHIVE);
-}
-
 int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
 {
     const int nf = B.nf;
@@ -592,8 +581,7 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     if (B.tot_hch) {
         HIP_TRY(launch_huff_prep(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, s));
         HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
-        hipLaunchKernelGGL(k_words_check, dim3((nf + 63) / 64), dim3(64), 0, s, B.d_fd, nf, B.d_wcnt);
-        HIP_TRY(hipGetLastError());
+        HIP_TRY(launch_words_check(B.d_fd, nf, B.d_wcnt, s));
         T.mark("dectab");
         HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, s));
         T.mark("huffman_decode");
@@ -716,6 +704,7 @@ int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const e
     Timer T(stats, s);
     st = enqueue_compress(B, P, s, T);
     if (st) return st;
+    T.mark("end");
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);
     if (st) return st;
@@ -819,6 +808,7 @@ int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t 
     Timer T(stats, s);
     st = decompress_impl(H, d_archive, size, d_out, out_elems, d_ws, ws_bytes, s, B, T);
     if (st) return st;
+    T.mark("end");
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);
     if (st) return st;

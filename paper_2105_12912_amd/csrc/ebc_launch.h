@@ -5,7 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "ebc_dev.h"
+#include "ebc_types.h"
 
 namespace ebc {
 
@@ -38,6 +38,7 @@ hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t
                             hipStream_t s);
 hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_t hc,
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s);
+hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, hipStream_t s);
 hipError_t launch_huff_prep(const FieldDesc* F, int nf, uint32_t units, uint32_t* wcnt, hipStream_t s);
 hipError_t launch_huff_decode(const FieldDesc* F, int nf, uint32_t units, const uint32_t* woff,
                               const uint8_t* tabs, size_t tab_stride, hipStream_t s);

@@ -1,0 +1,140 @@
+// ebc_types.h -- descriptors shared by the host planner and the HIP kernels.
+//
+// Work decomposition: every kernel covers all fields of a batch in one grid.
+// Each field owns a contiguous range of the grid's work units of that kernel
+// (FieldDesc::*_base); a workgroup finds its field with a binary search over
+// those bases.  A single-field call is simply a batch of one.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+// Device code sees every buffer pointer of a descriptor in the global address
+// space, so accesses compile to global_* instructions (a flat access would
+// also count against the LDS wait counter and serialise LDS work behind HBM).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define EBC_G __attribute__((address_space(1)))
+#else
+#define EBC_G
+#endif
+
+namespace ebc {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                 // threads per workgroup everywhere
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr uint32_t kHdr = 128;              // archive header bytes
+constexpr uint32_t kMaxBins = 4096;         // n_bins this GPU path implements
+constexpr uint32_t kMaxHc = 4096;           // Huffman chunk symbols implemented
+constexpr uint32_t kRangeUnit = 16384;      // elements per value-range work unit
+constexpr uint32_t kRleTile = 4096;         // elements per RLE work unit
+constexpr int kLutBits = 12;                // Huffman decode table width (bits looked up at once)
+constexpr int kMaxDecodeLen = 60;
+constexpr int kLongLens = 16;              // long-code lengths compared in registers           // longest code the decoder accepts (N < 2^32 gives <= 46)
+
+enum : int32_t { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2 };
+enum : int32_t { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2 };
+enum : int32_t { MODE_ABS = 0, MODE_REL = 1 };
+enum : int32_t {
+    ST_OK = 0,
+    ST_ERR_EB_TOO_SMALL = -4,
+    ST_ERR_EB = -3,
+    ST_ERR_NONFINITE = -6,
+    ST_ERR_OUT_TOO_SMALL = -7,
+    ST_ERR_ARCHIVE = -9,
+    ST_ERR_UNSUPPORTED = -11,
+};
+
+// Scalars produced on the device, one record per field.
+struct FieldDyn {
+    int32_t status;
+    int32_t codec;
+    float mn, mx;
+    double eb_abs, ebx2, inv;
+    uint64_t n_out;
+    uint64_t n_runs;
+    uint64_t n_words;
+    uint64_t huff_bits;
+    uint64_t total;
+    uint64_t off_bits, off_words, off_rlen, off_oidx, off_oval;
+    uint32_t max_len;
+    uint32_t n_used;  // symbols with a non-zero count
+    uint64_t zero_count;
+    uint64_t pad[2];
+};
+
+// Static description of one field: geometry, buffers, work bases.
+struct FieldDesc {
+    uint64_t n;
+    uint32_t nx, ny, nz;
+    int32_t rank;
+    uint32_t n_bins;
+    uint32_t hc;
+    int32_t eb_mode;
+    int32_t codec_req;
+    double eb;
+    // construct / reconstruct wave-tile geometry
+    uint32_t lx;             // lanes along x (each lane owns 4 consecutive x)
+    uint32_t nxb, nyb, nzb;  // wave-tile grid
+    uint32_t n_wave_tiles;
+    uint32_t vec;            // 1: rows 16-byte aligned, quads never straddle rows
+    // buffers (device)
+    const EBC_G float* in;   // compress input
+    EBC_G float* outf;       // decompress output
+    EBC_G uint8_t* arc;      // archive (compress output / decompress input)
+    uint64_t arc_cap;        // compress: capacity; decompress: archive size
+    EBC_G uint16_t* q;       // quant-codes, n
+    EBC_G int32_t* dsc;      // outlier delta scratch, n (dense, sparsely written)
+    EBC_G uint32_t* hist;    // n_bins
+    EBC_G uint32_t* hpart;   // wg_tiles * n_bins partial histograms
+    EBC_G uint32_t* rpart;   // range partials: 3 words per range unit
+    EBC_G uint64_t* code;    // n_bins packed codewords: (len << 56) | code
+    EBC_G uint8_t* len;      // n_bins code lengths
+    EBC_G uint32_t* hbits;   // per Huffman chunk bit counts
+    EBC_G uint32_t* rstart;  // RLE run starts (compress scratch)
+    EBC_G uint32_t* zpart;   // per WG-tile zero counts (decompress validation)
+    EBC_G FieldDyn* dyn;
+    // this field's work units in each batch-wide index space
+    uint32_t range_units, range_base;  // value range / fill: kRangeUnit elements per WG
+    uint32_t wg_tiles, wg_base;        // construct / reconstruct WG tiles (rank group relative)
+    uint32_t n_seg, seg_base;          // outlier segments: count-array entries
+    uint32_t ow_units, ow_base;        // outlier write: 1024 segments per WG
+    uint32_t n_hch, hch_base;          // Huffman chunks: word-count array entries
+    uint32_t hwg_units, hwg_base;      // Huffman encode: huff_cpw(hc) chunks per WG
+    uint32_t hdwg_units, hdwg_base;    // Huffman decode: 256 chunks per WG
+    uint32_t n_rt, rt_base;            // RLE tiles of kRleTile elements (count array / WG)
+    uint32_t n_runs_hdr, rle_base;     // decompress: runs in the archive (start array entries)
+    uint32_t sc_units, sc_base;        // decompress outlier scatter: 256 outliers per WG
+    uint32_t rl_units, rl_base;        // decompress run-length prep: 256 runs per WG
+    // decompress: header values
+    uint64_t n_out_hdr;
+    uint64_t n_words_hdr;
+    double ebx2_hdr;
+    float cval;
+    int32_t codec_hdr;
+    uint64_t off_bits, off_words, off_val, off_rlen, off_oidx, off_oval;
+};
+
+// Canonical Huffman decoder tables of one field (built by k_dectab).
+// lut[p] decodes the next kLutBits stream bits p into up to three whole
+// codewords: bits 0-11/12-23/24-35 symbols, 36-39/40-43/44-47 their lengths,
+// 48-49 how many (0 = the first codeword is longer than kLutBits),
+// 50-55 their total length.  Symbols fit 12 bits because n_bins <= 4096.
+struct DecTab {
+    uint64_t first[65];   // first code of each length
+    uint64_t endv[65];    // (first[L] + count[L]) << (64 - L): a left-aligned window w holds a
+                          // code of length <= L iff w < endv[L] (defined for L < max_len)
+    uint32_t count[65];   // codes of each length
+    uint32_t offset[65];  // index of the first symbol of each length in perm
+    uint32_t max_len;
+    uint32_t pad;
+    uint64_t lut[1u << kLutBits];
+    uint16_t perm[kMaxBins];  // symbols ordered by (length, symbol)
+};
+
+__host__ __device__ constexpr uint32_t huff_cpw(uint32_t hc) { return hc <= 1024 ? 4 : 4096 / hc; }
+
+__host__ __device__ constexpr size_t dectab_bytes() { return (sizeof(DecTab) + 255) & ~(size_t)255; }
+
+}  // namespace ebc

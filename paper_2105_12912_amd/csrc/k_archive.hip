@@ -19,7 +19,7 @@ __global__ void k_layout(const FieldDesc* __restrict__ F, int nf, const uint32_t
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     const FieldDesc& fd = F[f];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK) return;
     if (dy->codec == ARC_CONST) {
         dy->total = kHdr;
@@ -49,7 +49,7 @@ __global__ void k_layout(const FieldDesc* __restrict__ F, int nf, const uint32_t
     if (dy->total > fd.arc_cap) dy->status = ST_ERR_OUT_TOO_SMALL;
 }
 
-__device__ __forceinline__ void zero_gap(uint8_t* a, uint64_t from, uint64_t to, int lane)
+__device__ __forceinline__ void zero_gap(EBC_G uint8_t* a, uint64_t from, uint64_t to, int lane)
 {
     for (uint64_t i = from + lane; i < to; i += kWave) a[i] = 0;
 }
@@ -60,9 +60,9 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
 {
     const int f = blockIdx.x;
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK) return;
-    uint8_t* a = fd.arc;
+    EBC_G uint8_t* a = fd.arc;
     const int l = threadIdx.x;
     __shared__ uint32_t h[32];
     if (l < 32) h[l] = 0;
@@ -99,7 +99,7 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
         }
     }
     __syncthreads();
-    if (l < 32) ((uint32_t*)a)[l] = h[l];
+    if (l < 32) ((EBC_G uint32_t*)a)[l] = h[l];
     if (dy->codec == ARC_CONST) return;
     const uint64_t no = dy->n_out;
     if (dy->codec == ARC_HUFFMAN) {
@@ -118,7 +118,7 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
 // Async result record: archive size (0 on error) and status.
 __global__ void k_result(const FieldDesc* __restrict__ F, uint64_t* __restrict__ res)
 {
-    const FieldDyn* dy = F[0].dyn;
+    const EBC_G FieldDyn* dy = F[0].dyn;
     res[0] = dy->status == ST_OK ? dy->total : 0ull;
     ((int32_t*)(res + 1))[0] = dy->status;
     ((int32_t*)(res + 1))[1] = dy->codec;

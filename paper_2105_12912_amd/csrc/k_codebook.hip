@@ -78,7 +78,7 @@ __device__ void canonical_rank(const uint8_t* len_s, uint32_t nb, uint16_t* cnt,
 __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.x];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const uint32_t nb = fd.n_bins;
     const uint32_t P = pow2ceil(nb);
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
                                                    uint8_t* __restrict__ tabs)
 {
     const FieldDesc& fd = F[blockIdx.x];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
     DecTab* T = (DecTab*)(tabs + (size_t)blockIdx.x * dectab_bytes());
     const uint32_t nb = fd.n_bins;
@@ -306,15 +306,37 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += kBlock) T->perm[i] = perm_s[i];
+    // left-aligned ends of the code space of lengths <= L (monotone in L)
+    __syncthreads();
+    if (threadIdx.x <= 64) {
+        const uint32_t L = threadIdx.x;
+        const uint32_t maxl = T->max_len;
+        uint64_t endv = ~0ull;
+        if (L >= 1 && L < maxl) endv = (first[L] + cntL[L]) << (64 - L);
+        T->endv[L] = endv;
+    }
+    // multi-symbol lookup table
     for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kBlock) {
-        uint32_t e = 0;
-        for (int L = 1; L <= kLutBits; ++L) {
-            const uint64_t v = p >> (kLutBits - L);
-            if (cntL[L] && v < first[L] + cntL[L]) {
-                e = ((uint32_t)perm_s[offs[L] + (uint32_t)(v - first[L])] << 8) | (uint32_t)L;
-                break;
+        uint64_t e = 0;
+        uint32_t pos = 0, n = 0;
+        while (n < 3) {
+            uint32_t L = 0, sym = 0;
+            for (uint32_t l = 1; l + pos <= (uint32_t)kLutBits; ++l) {
+                const uint64_t v = (p >> (kLutBits - pos - l)) & ((1u << l) - 1);
+                if (cntL[l] && v < first[l] + cntL[l]) {
+                    L = l;
+                    sym = perm_s[offs[l] + (uint32_t)(v - first[l])];
+                    break;
+                }
             }
+            if (!L) break;
+            e |= (uint64_t)sym << (12 * n);
+            e |= (uint64_t)L << (36 + 4 * n);
+            pos += L;
+            ++n;
         }
+        e |= (uint64_t)n << 48;
+        e |= (uint64_t)pos << 50;
         T->lut[p] = e;
     }
 }

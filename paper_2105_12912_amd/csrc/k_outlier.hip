@@ -40,13 +40,13 @@ __global__ __launch_bounds__(kBlock) void k_outlier_write(const FieldDesc* __res
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::ow_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST || dy->n_out == 0) return;
     const int l = lane_id();
     const uint32_t* off = soff + fd.seg_base;
     const uint32_t off0 = off[0];
-    uint32_t* oidx = (uint32_t*)(fd.arc + dy->off_oidx);
-    int32_t* oval = (int32_t*)(fd.arc + dy->off_oval);
+    EBC_G uint32_t* oidx = (EBC_G uint32_t*)(fd.arc + dy->off_oidx);
+    EBC_G int32_t* oval = (EBC_G int32_t*)(fd.arc + dy->off_oval);
     const uint32_t s_lo = (t - fd.ow_base) * kSegPerBlock + (threadIdx.x / kWave) * kSegPerWave;
     for (uint32_t sb = s_lo; sb < s_lo + kSegPerWave && sb < fd.n_seg; sb += kWave) {
         const uint32_t s = sb + l;
@@ -87,12 +87,12 @@ __global__ __launch_bounds__(kBlock) void k_outlier_scatter(const FieldDesc* __r
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::sc_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || fd.codec_hdr == ARC_CONST) return;
     const uint64_t k = (uint64_t)(t - fd.sc_base) * kBlock + threadIdx.x;
     if (k >= fd.n_out_hdr) return;
-    const uint32_t* oidx = (const uint32_t*)(fd.arc + fd.off_oidx);
-    const int32_t* oval = (const int32_t*)(fd.arc + fd.off_oval);
+    const EBC_G uint32_t* oidx = (const EBC_G uint32_t*)(fd.arc + fd.off_oidx);
+    const EBC_G int32_t* oval = (const EBC_G int32_t*)(fd.arc + fd.off_oval);
     const uint32_t i = oidx[k];
     bool bad = i >= fd.n || (k > 0 && oidx[k - 1] >= i);
     if (!bad) bad = fd.q[i] != 0;

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_range(const FieldDesc* __restrict__ 
     const FieldDesc& fd = F[f];
     const uint64_t lo = (uint64_t)(u - fd.range_base) * kRangeUnit;
     const uint64_t hi = min(lo + (uint64_t)kRangeUnit, fd.n);
-    const float* __restrict__ in = fd.in;
+    const EBC_G float* __restrict__ in = fd.in;
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, bad = 0u;
     const bool aligned = ((uintptr_t)in & 15u) == 0;
     for (uint64_t i = lo + 4u * threadIdx.x; i < hi; i += 4u * kBlock) {
@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_range(const FieldDesc* __restrict__ 
             kmax = max(kmax, s_red[1][k]);
             bad |= s_red[2][k];
         }
-        uint32_t* rp = fd.rpart + 3ull * (u - fd.range_base);
+        EBC_G uint32_t* rp = fd.rpart + 3ull * (u - fd.range_base);
         rp[0] = kmin, rp[1] = kmax, rp[2] = bad;
     }
 }
@@ -96,11 +96,11 @@ __device__ __forceinline__ int ilogb_pos(double x)
 __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.x];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     for (uint32_t b = threadIdx.x; b < fd.n_bins; b += kBlock) fd.hist[b] = 0;
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, bad = 0u;
     for (uint32_t u = threadIdx.x; u < fd.range_units; u += kBlock) {
-        const uint32_t* rp = fd.rpart + 3ull * u;
+        const EBC_G uint32_t* rp = fd.rpart + 3ull * u;
         kmin = min(kmin, rp[0]);
         kmax = max(kmax, rp[1]);
         bad |= rp[2];
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
 
 // ------------------------------------------------------ Lorenzo construct
 template <bool VEC>
-__device__ __forceinline__ void load_quad(const float* __restrict__ p, uint64_t i, int nvalid,
+__device__ __forceinline__ void load_quad(const EBC_G float* __restrict__ p, uint64_t i, int nvalid,
                                           float v[4])
 {
     if (VEC) {
@@ -178,7 +178,7 @@ __device__ __forceinline__ void load_quad(const float* __restrict__ p, uint64_t 
 }
 
 template <bool VEC>
-__device__ __forceinline__ void store_codes(uint16_t* __restrict__ q, uint64_t i, int nvalid,
+__device__ __forceinline__ void store_codes(EBC_G uint16_t* __restrict__ q, uint64_t i, int nvalid,
                                             const uint32_t c[4])
 {
     if (VEC) {
@@ -186,7 +186,7 @@ __device__ __forceinline__ void store_codes(uint16_t* __restrict__ q, uint64_t i
             uint2 t;
             t.x = c[0] | (c[1] << 16);
             t.y = c[2] | (c[3] << 16);
-            *(uint2*)(q + i) = t;
+            *(EBC_G uint2*)(q + i) = t;
         }
     } else {
 #pragma unroll
@@ -211,7 +211,7 @@ __device__ __forceinline__ void prequant4(const float v[4], double inv, int32_t 
 // postquant one quad of deltas: code, outlier scratch, histogram.
 // Returns a 4-bit mask of outliers among the valid elements.
 __device__ __forceinline__ uint32_t postquant4(const int32_t dl[4], int nvalid, QuantCtx& qc,
-                                               uint32_t c[4], int32_t* __restrict__ dsc,
+                                               uint32_t c[4], EBC_G int32_t* __restrict__ dsc,
                                                uint64_t i, uint32_t* sh_hist)
 {
     uint32_t om = 0;
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const uint32_t nb = fd.n_bins;
     for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh_hist[b] = 0;
@@ -263,9 +263,9 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
     qc.center = 0;
     const int l = lane_id();
     const uint32_t wt = (t - fd.wg_base) * kWavesPerBlock + threadIdx.x / kWave;
-    const float* __restrict__ in = fd.in;
-    uint16_t* __restrict__ qo = fd.q;
-    int32_t* __restrict__ dsc = fd.dsc;
+    const EBC_G float* __restrict__ in = fd.in;
+    EBC_G uint16_t* __restrict__ qo = fd.q;
+    EBC_G int32_t* __restrict__ dsc = fd.dsc;
     uint32_t* __restrict__ segs = seg_cnt + fd.seg_base;
 
     if (wt < fd.n_wave_tiles) {
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
     const uint32_t cs = wave_sum_u32(qc.center);
     if (l == 0 && cs) atomicAdd(&sh_hist[qc.r], cs);
     __syncthreads();
-    uint32_t* hp = fd.hpart + (uint64_t)(t - fd.wg_base) * nb;
+    EBC_G uint32_t* hp = fd.hpart + (uint64_t)(t - fd.wg_base) * nb;
     for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hp[b] = sh_hist[b];
 }
 

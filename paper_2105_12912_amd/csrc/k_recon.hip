@@ -19,7 +19,7 @@
 namespace ebc {
 
 template <bool VEC>
-__device__ __forceinline__ void load_codes(const uint16_t* __restrict__ q, uint64_t i, int nvalid,
+__device__ __forceinline__ void load_codes(const EBC_G uint16_t* __restrict__ q, uint64_t i, int nvalid,
                                            uint32_t c[4])
 {
     if (VEC) {
@@ -36,7 +36,7 @@ __device__ __forceinline__ void load_codes(const uint16_t* __restrict__ q, uint6
 }
 
 template <bool VEC>
-__device__ __forceinline__ void store_quad(float* __restrict__ o, uint64_t i, int nvalid,
+__device__ __forceinline__ void store_quad(EBC_G float* __restrict__ o, uint64_t i, int nvalid,
                                            const float v[4])
 {
     if (VEC) {
@@ -50,7 +50,7 @@ __device__ __forceinline__ void store_quad(float* __restrict__ o, uint64_t i, in
 
 // q' for a quad: code - r, or the exact outlier delta where the code is 0
 __device__ __forceinline__ void fuse4(const uint32_t c[4], int nvalid, int32_t r,
-                                      const int32_t* __restrict__ dsc, uint64_t i, uint32_t qp[4],
+                                      const EBC_G int32_t* __restrict__ dsc, uint64_t i, uint32_t qp[4],
                                       uint32_t& zeros)
 {
 #pragma unroll
@@ -76,15 +76,15 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const int l = lane_id();
     const uint32_t wt = (t - fd.wg_base) * kWavesPerBlock + threadIdx.x / kWave;
     const int32_t r = (int32_t)(fd.n_bins / 2);
     const double ebx2 = dy->ebx2;
-    const uint16_t* __restrict__ q = fd.q;
-    const int32_t* __restrict__ dsc = fd.dsc;
-    float* __restrict__ out = fd.outf;
+    const EBC_G uint16_t* __restrict__ q = fd.q;
+    const EBC_G int32_t* __restrict__ dsc = fd.dsc;
+    EBC_G float* __restrict__ out = fd.outf;
     uint32_t zeros = 0;
 
     if (wt < fd.n_wave_tiles) {
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
 __global__ __launch_bounds__(kBlock) void k_recon_check(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.x];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || fd.codec_hdr == ARC_CONST) return;
     uint64_t z = 0;
     for (uint32_t i = threadIdx.x; i < fd.wg_tiles; i += kBlock) z += fd.zpart[i];

@@ -20,10 +20,10 @@ __device__ __forceinline__ uint32_t run_flags(const FieldDesc& fd, uint64_t lo, 
     __shared__ uint16_t s_last[kBlock];
     const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
     const uint64_t n = fd.n;
-    const uint16_t* __restrict__ q = fd.q;
+    const EBC_G uint16_t* __restrict__ q = fd.q;
     if (i0 + kRleItems <= n) {
-        const uint4 a = *(const uint4*)(q + i0);
-        const uint4 b = *(const uint4*)(q + i0 + 8);
+        const uint4 a = *(const EBC_G uint4*)(q + i0);
+        const uint4 b = *(const EBC_G uint4*)(q + i0 + 8);
         const uint32_t w[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int k = 0; k < 8; ++k) c[2 * k] = w[k] & 0xFFFF, c[2 * k + 1] = w[k] >> 16;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restric
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
     uint16_t c[kRleItems];
     const uint32_t flags = run_flags(fd, (uint64_t)(t - fd.rt_base) * kRleTile, c);
@@ -92,14 +92,14 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
     const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
     uint16_t c[kRleItems];
     const uint32_t flags = run_flags(fd, lo, c);
     uint32_t tot;
     uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
-    uint16_t* val = (uint16_t*)(fd.arc + kHdr);
+    EBC_G uint16_t* val = (EBC_G uint16_t*)(fd.arc + kHdr);
     const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
 #pragma unroll
     for (int k = 0; k < kRleItems; ++k) {
@@ -115,10 +115,10 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
 __global__ __launch_bounds__(kBlock) void k_rle_len(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.y];
-    const FieldDyn* dy = fd.dyn;
+    const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
     const uint64_t R = dy->n_runs;
-    uint32_t* len = (uint32_t*)(fd.arc + dy->off_rlen);
+    EBC_G uint32_t* len = (EBC_G uint32_t*)(fd.arc + dy->off_rlen);
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < R;
          k += (uint64_t)gridDim.x * kBlock) {
         const uint64_t end = k + 1 < R ? fd.rstart[k + 1] : fd.n;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_prep(const FieldDesc* __restrict
     const FieldDesc& fd = F[f];
     const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
     if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
-    const uint32_t L = ((const uint32_t*)(fd.arc + fd.off_rlen))[k];
+    const uint32_t L = ((const EBC_G uint32_t*)(fd.arc + fd.off_rlen))[k];
     if (L == 0) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
     starts[fd.rle_base + k] = L;
 }
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    FieldDyn* dy = fd.dyn;
+    EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || fd.codec_hdr != ARC_RLE) return;
     const uint32_t* S = starts + fd.rle_base;
     const uint32_t s0 = S[0];
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     }
     __syncthreads();
     const uint32_t rlo = s_rlo, nr = s_nr;  // nr <= kRleTile because every run is non-empty
-    const uint16_t* val = (const uint16_t*)(fd.arc + fd.off_val);
+    const EBC_G uint16_t* val = (const EBC_G uint16_t*)(fd.arc + fd.off_val);
     for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
         s_start[i] = S[rlo + i] - s0;
         s_val[i] = val[rlo + i];
@@ -210,15 +210,15 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
         while (a + 1 < nr && (uint64_t)s_start[a + 1] <= i) ++a;
         c[k] = s_val[a];
     }
-    uint16_t* __restrict__ q = fd.q;
+    EBC_G uint16_t* __restrict__ q = fd.q;
     if (i0 + kRleItems <= hi) {
         uint4 x, y;
         x.x = c[0] | ((uint32_t)c[1] << 16), x.y = c[2] | ((uint32_t)c[3] << 16);
         x.z = c[4] | ((uint32_t)c[5] << 16), x.w = c[6] | ((uint32_t)c[7] << 16);
         y.x = c[8] | ((uint32_t)c[9] << 16), y.y = c[10] | ((uint32_t)c[11] << 16);
         y.z = c[12] | ((uint32_t)c[13] << 16), y.w = c[14] | ((uint32_t)c[15] << 16);
-        *(uint4*)(q + i0) = x;
-        *(uint4*)(q + i0 + 8) = y;
+        *(EBC_G uint4*)(q + i0) = x;
+        *(EBC_G uint4*)(q + i0 + 8) = y;
     } else {
         for (int k = 0; k < kRleItems; ++k)
             if (i0 + k < hi) q[i0 + k] = c[k];

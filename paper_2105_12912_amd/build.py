@@ -15,6 +15,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libebc.so")
 ARCH = os.environ.get("EBC_OFFLOAD_ARCH", "gfx950")
@@ -44,7 +45,7 @@ def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
     if src.endswith(".cpp"):
         cmd = [HIPCC, "-x", "c++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
-               "-I", ROCM_INCLUDE,
+               "-I", ROCM_INCLUDE, "-I", INCLUDE,
                "-c", os.path.join(CSRC, src), "-o", obj]
     else:
         cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]

@@ -16,7 +16,7 @@
 #include <cstring>
 #include <vector>
 
-#include "../../include/ebc.h"
+#include "ebc.h"
 #include "ebc_types.h"
 #include "ebc_launch.h"
 

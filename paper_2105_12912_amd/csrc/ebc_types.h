@@ -118,9 +118,9 @@ struct FieldDesc {
 
 // Canonical Huffman decoder tables of one field (built by k_dectab).
 // lut[p] decodes the next kLutBits stream bits p into up to three whole
-// codewords: bits 0-11/12-23/24-35 symbols, 36-39/40-43/44-47 their lengths,
-// 48-49 how many (0 = the first codeword is longer than kLutBits),
-// 50-55 their total length.  Symbols fit 12 bits because n_bins <= 4096.
+// codewords: bits 0-15/16-31/32-47 the symbols (zero when absent), 48-49 how
+// many (0 = the first codeword is longer than kLutBits), 50-55 their total
+// length, 56-59 and 60-63 the lengths of the first two.
 struct DecTab {
     uint64_t first[65];   // first code of each length
     uint64_t endv[65];    // (first[L] + count[L]) << (64 - L): a left-aligned window w holds a

@@ -330,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
                 }
             }
             if (!L) break;
-            e |= (uint64_t)sym << (12 * n);
-            e |= (uint64_t)L << (36 + 4 * n);
+            e |= (uint64_t)sym << (16 * n);
+            if (n < 2) e |= (uint64_t)L << (56 + 4 * n);
             pos += L;
             ++n;
         }

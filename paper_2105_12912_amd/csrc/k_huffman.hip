@@ -157,13 +157,24 @@ __device__ __forceinline__ uint64_t window_at(const EBC_G uint32_t* __restrict__
     return a;
 }
 
-// In-order stream of a chunk's 32-bit words, fetched as aligned 16-byte
-// blocks one block ahead of use: each lane issues one vector load per four
-// words consumed, so the wait at a refill rarely finds the load outstanding.
-struct WordQueue {
-    const EBC_G uint4* __restrict__ blk;  // aligned 16-byte blocks covering the chunk
-    uint32_t nblk, jn, have;
-    uint32_t q0, q1, q2, q3, q4, q5, q6, q7;
+// Per-lane ring of the chunk's 32-bit stream words in LDS.  Words reach the
+// ring in 16-byte blocks: a block is loaded into registers and written to the
+// ring at the next wave-uniform refill point, kRefillEvery iterations later,
+// so its load has long completed when it is waited for.  Bit refills then
+// read LDS; a lane that outruns its ring reads global memory directly.
+constexpr uint32_t kRingWords = 32;
+constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: no bank conflicts across lanes
+constexpr uint32_t kRefillEvery = 4;
+
+struct WordRing {
+    uint32_t* ring;                        // this lane's slots in LDS
+    const EBC_G uint4* __restrict__ blk;   // aligned 16-byte blocks of the stream
+    const EBC_G uint32_t* __restrict__ words;
+    uint32_t nw, o, nblk;  // words, offset of word 0 inside block 0, blocks
+    uint32_t rd;           // next chunk word to hand out
+    uint32_t wr;           // block-coordinate words [wr - kRingWords, wr) are in the ring
+    uint32_t jn;           // block held in `pend`
+    uint4 pend;
     __device__ __forceinline__ uint4 fetch(uint32_t j) const
     {
         if (j < nblk) {
@@ -172,52 +183,108 @@ struct WordQueue {
         }
         return make_uint4(0u, 0u, 0u, 0u);
     }
-    __device__ __forceinline__ void init(const EBC_G uint32_t* __restrict__ words, uint32_t nw)
+    // Stream word i.  The value always comes out of the ring slot, so the
+    // common path never waits on global memory; a lane that outran the ring
+    // first copies the word into the (already consumed) slot.
+    __device__ __forceinline__ uint32_t get(uint32_t i)
     {
-        const uintptr_t a = (uintptr_t)words;
-        const uint32_t o = (uint32_t)((a & 15u) >> 2);
+        const uint32_t a = i + o;
+        const uint32_t slot = a % kRingWords;
+        if (!(a < wr && a + kRingWords >= wr)) ring[slot] = i < nw ? words[i] : 0u;
+        return ring[slot];
+    }
+    __device__ __forceinline__ void init(uint32_t* r, const EBC_G uint32_t* __restrict__ w, uint32_t n)
+    {
+        ring = r;
+        words = w;
+        nw = n;
+        const uintptr_t a = (uintptr_t)w;
+        o = (uint32_t)((a & 15u) >> 2);
         blk = (const EBC_G uint4*)(a & ~(uintptr_t)15u);
         nblk = (o + nw + 3) / 4;
-        const uint4 b0 = fetch(0), b1 = fetch(1);
-        q0 = b0.x, q1 = b0.y, q2 = b0.z, q3 = b0.w, q4 = b1.x, q5 = b1.y, q6 = b1.z, q7 = b1.w;
-        jn = 2;
-        have = 8;
-        for (uint32_t i = 0; i < o; ++i) pop();
-    }
-    __device__ __forceinline__ uint32_t pop()
-    {
-        const uint32_t w = q0;
-        q0 = q1, q1 = q2, q2 = q3, q3 = q4, q4 = q5, q5 = q6, q6 = q7;
-        if (--have == 4) {
-            const uint4 b = fetch(jn++);
-            q4 = b.x, q5 = b.y, q6 = b.z, q7 = b.w;
-            have = 8;
+        for (uint32_t j = 0; j < kRingWords / 4; ++j) {
+            const uint4 b = fetch(j);
+            ring[4 * j + 0] = b.x, ring[4 * j + 1] = b.y, ring[4 * j + 2] = b.z, ring[4 * j + 3] = b.w;
         }
-        return w;
+        wr = kRingWords;
+        jn = kRingWords / 4;
+        pend = fetch(jn);
+        rd = 0;
+    }
+    __device__ __forceinline__ uint32_t pop() { return get(rd++); }
+    // wave-uniform refill point: move the pending block in if its slots are consumed
+    __device__ __forceinline__ void refill()
+    {
+        if (jn < nblk && wr + 4 <= rd + o + kRingWords) {
+            uint32_t* d = ring + (wr % kRingWords);
+            d[0] = pend.x, d[1] = pend.y, d[2] = pend.z, d[3] = pend.w;
+            wr += 4;
+            ++jn;
+            pend = fetch(jn);
+        }
     }
 };
 
-// Appends symbols to a 128-bit register pack and stores every 8 (16 bytes,
-// aligned because chunks start at multiples of 8 symbols).
-struct SymPack {
-    uint64_t lo = 0, hi = 0;
+// Output accumulator: up to 7 pending 16-bit symbols in a0/a1 plus overflow
+// in a2; appending up to three symbols is branch-free, and every full group
+// of 8 leaves as one aligned 16-byte store (chunks start at multiples of 8).
+struct SymAcc {
+    uint64_t a0 = 0, a1 = 0, a2 = 0;
     uint32_t cnt = 0, base = 0;
-    __device__ __forceinline__ void push(EBC_G uint16_t* __restrict__ out, uint32_t s)
+    __device__ __forceinline__ void append(EBC_G uint16_t* __restrict__ out, uint64_t syms, uint32_t n)
     {
-        if (cnt < 4) lo |= (uint64_t)s << (16 * cnt);
-        else hi |= (uint64_t)s << (16 * (cnt - 4));
-        if (++cnt == 8) {
+        const uint32_t s = 16 * cnt;  // 0..112
+        const uint32_t s0 = s & 63;
+        const uint64_t lo = syms << s0;
+        const uint64_t hi = s0 ? syms >> (64 - s0) : 0ull;
+        if (s < 64) {
+            a0 |= lo;
+            a1 |= hi;
+        } else {
+            a1 |= lo;
+            a2 |= hi;
+        }
+        cnt += n;
+        if (cnt >= 8) {
             *(EBC_G uint4*)(out + base) =
-                make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+                make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
             base += 8;
-            lo = hi = 0;
-            cnt = 0;
+            cnt -= 8;
+            a0 = a2;
+            a1 = 0;
+            a2 = 0;
         }
     }
     __device__ __forceinline__ void flush(EBC_G uint16_t* __restrict__ out)
     {
         for (uint32_t k = 0; k < cnt; ++k)
-            out[base + k] = (uint16_t)((k < 4 ? lo >> (16 * k) : hi >> (16 * (k - 4))) & 0xFFFF);
+            out[base + k] = (uint16_t)((k < 4 ? a0 >> (16 * k) : a1 >> (16 * (k - 4))) & 0xFFFF);
+    }
+};
+
+// One codeword longer than kLutBits at the head of a window: its length is
+// kLutBits + 1 plus the number of code-space ends the window lies at or above.
+// Returns the length (0 if the bits are not a codeword) and the symbol.
+struct LongCode {
+    const uint64_t* ev;  // ends of lengths kLutBits+1 .. kLutBits+kLongLens (wave-uniform)
+    uint32_t nlong, maxl;
+    const uint64_t* s_endv;
+    const uint64_t* s_first;
+    const uint32_t* s_off;
+    const uint16_t* perm;
+    __device__ __forceinline__ uint32_t decode(uint64_t w, uint32_t& sym) const
+    {
+        uint32_t L = kLutBits + 1;
+#pragma unroll
+        for (int k = 0; k < kLongLens; ++k)
+            if ((uint32_t)k < nlong) L += w >= ev[k] ? 1u : 0u;
+        for (uint32_t l = kLutBits + 1 + kLongLens; l < maxl; ++l) L += w >= s_endv[l] ? 1u : 0u;
+        // the window is at or above the first length-L code by construction;
+        // it must also be below the end of the length-L codes
+        const uint64_t d = (w >> (64 - L)) - s_first[L];
+        if (d >= (uint64_t)(s_off[L + 1] - s_off[L])) return 0;
+        sym = perm[s_off[L] + (uint32_t)d];
+        return L;
     }
 };
 
@@ -231,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
     __shared__ uint64_t s_first[65];
     __shared__ uint64_t s_endv[65];
     __shared__ uint32_t s_off[65];
+    __shared__ uint32_t s_ring[kBlock * kRingStride];
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
@@ -245,9 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
         s_off[threadIdx.x] = T->offset[threadIdx.x];
     }
     const uint32_t maxl = T->max_len;
-    // ends of the first kLongLens long lengths, wave-uniform (scalar registers)
     uint64_t ev[kLongLens];
-    const uint32_t nlong = maxl > kLutBits + 1 ? maxl - kLutBits - 1 : 0;
 #pragma unroll
     for (int k = 0; k < kLongLens; ++k) ev[k] = T->endv[kLutBits + 1 + k];
     __syncthreads();
@@ -266,84 +332,89 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
     const uint64_t lo = (uint64_t)c * hc;
     const uint32_t nsym = (uint32_t)min<uint64_t>(hc, fd.n - lo);
     EBC_G uint16_t* __restrict__ out = fd.q + lo;
+    const LongCode lc{ev, maxl > kLutBits + 1 ? maxl - kLutBits - 1 : 0u, maxl,
+                      s_endv, s_first, s_off, perm};
 
-    // 64-bit window fed from the block queue
-    WordQueue wq;
-    wq.init(words, nw);
-    uint64_t buf = (uint64_t)wq.pop() << 32;
-    buf |= wq.pop();
-    uint32_t valid = 64, pos = 0, j = 0;
+    WordRing wr;
+    wr.init(s_ring + threadIdx.x * kRingStride, words, nw);
+    uint64_t buf = (uint64_t)wr.pop() << 32;
+    buf |= wr.pop();
+    uint32_t valid = 64, pos = 0, j = 0, it = 0;
     bool bad = false;
-    SymPack pk;
-    while (j < nsym) {
+    SymAcc acc;
+    // main loop: at least three symbols left, so whole table entries are used
+    while (j + 3 <= nsym) {
+        if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
         if (valid < 32) {
-            buf |= (uint64_t)wq.pop() << (32 - valid);
+            buf |= (uint64_t)wr.pop() << (32 - valid);
             valid += 32;
         }
         const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
         uint32_t n = (uint32_t)(e >> 48) & 3u;
-        const bool slow = n == 0;
-        if (!slow) {
-            const uint32_t rem = nsym - j;
-            uint32_t tl = (uint32_t)(e >> 50) & 63u;
-            if (n > rem) {
-                n = rem;
-                tl = (uint32_t)(e >> 36) & 15u;
-                if (n == 2) tl += (uint32_t)(e >> 40) & 15u;
+        uint32_t tl = (uint32_t)(e >> 50) & 63u;
+        uint64_t syms = e & 0xFFFFFFFFFFFFull;
+        if (n == 0) {
+            uint32_t sym = 0;
+            uint32_t L = lc.decode(buf, sym);
+            if (L == 0 || L > valid) {
+                // longer than the buffered bits (only codes > 32 bits): exact window
+                L = lc.decode(window_at(words, nw, pos), sym);
+                if (L == 0) {
+                    bad = true;
+                    break;
+                }
             }
-            pk.push(out, (uint32_t)e & 0xFFFu);
-            if (n > 1) pk.push(out, (uint32_t)(e >> 12) & 0xFFFu);
-            if (n > 2) pk.push(out, (uint32_t)(e >> 24) & 0xFFFu);
+            n = 1;
+            tl = L;
+            syms = sym;
+        }
+        acc.append(out, syms, n);
+        j += n;
+        pos += tl;
+        if (tl <= valid) {
             buf <<= tl;
             valid -= tl;
-            pos += tl;
-            j += n;
-        }
-        if (slow) {
-            // codeword longer than kLutBits: its length is kLutBits + 1 plus the
-            // number of longer code-space ends the window lies at or above
-            uint32_t L = kLutBits + 1;
-#pragma unroll
-            for (int k = 0; k < kLongLens; ++k)
-                if ((uint32_t)k < nlong) L += buf >= ev[k] ? 1u : 0u;
-            for (uint32_t l = kLutBits + 1 + kLongLens; l < maxl; ++l) L += buf >= s_endv[l] ? 1u : 0u;
-            if (L <= valid) {
-                // the window is at or above the start of the length-L codes by
-                // construction; it must also lie below their end
-                const uint64_t d = (buf >> (64 - L)) - s_first[L];
-                if (d >= (uint64_t)(s_off[L + 1] - s_off[L])) {
-                    bad = true;
-                    break;
-                }
-                pk.push(out, perm[s_off[L] + (uint32_t)d]);
-                buf <<= L;
-                valid -= L;
-                pos += L;
-                j += 1;
-            } else {
-                // longer than the buffered bits (> 32-bit codes) or invalid:
-                // exact window from memory, then resynchronise the buffer
-                const uint64_t win = window_at(words, nw, pos);
-                L = kLutBits + 1;
-                for (uint32_t l = kLutBits + 1; l < maxl; ++l) L += win >= s_endv[l] ? 1u : 0u;
-                const uint64_t d = (win >> (64 - L)) - s_first[L];
-                if (d >= (uint64_t)(s_off[L + 1] - s_off[L])) {
-                    bad = true;
-                    break;
-                }
-                pk.push(out, perm[s_off[L] + (uint32_t)d]);
-                pos += L;
-                j += 1;
-                const uint32_t kk = pos >> 5, s = pos & 31;
-                wq.init(words + kk, nw > kk ? nw - kk : 0u);
-                buf = (uint64_t)wq.pop() << 32;
-                buf |= wq.pop();
-                buf <<= s;
-                valid = 64 - s;
-            }
+        } else {
+            const uint32_t kk = pos >> 5, s = pos & 31;
+            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << s;
+            wr.rd = kk + 2;
+            valid = 64 - s;
         }
     }
-    if (!bad) pk.flush(out);
+    // tail: one codeword at a time
+    while (!bad && j < nsym) {
+        if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
+        if (valid < 32) {
+            buf |= (uint64_t)wr.pop() << (32 - valid);
+            valid += 32;
+        }
+        const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+        uint32_t sym = (uint32_t)e & 0xFFFFu;
+        uint32_t L = (uint32_t)(e >> 56) & 15u;
+        if (((e >> 48) & 3u) == 0) {
+            L = lc.decode(buf, sym);
+            if (L == 0 || L > valid) {
+                L = lc.decode(window_at(words, nw, pos), sym);
+                if (L == 0) {
+                    bad = true;
+                    break;
+                }
+            }
+        }
+        acc.append(out, sym, 1);
+        j += 1;
+        pos += L;
+        if (L <= valid) {
+            buf <<= L;
+            valid -= L;
+        } else {
+            const uint32_t kk = pos >> 5, s = pos & 31;
+            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << s;
+            wr.rd = kk + 2;
+            valid = 64 - s;
+        }
+    }
+    if (!bad) acc.flush(out);
     if (bad || pos > nbits) atomicMin(&dy->status, ST_ERR_ARCHIVE);
 }
 

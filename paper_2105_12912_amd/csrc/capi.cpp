@@ -99,44 +99,47 @@ int check_dims(int rank, const uint64_t dims[3], uint64_t* n)
 }
 
 // ------------------------------------------------------------------ geometry
-// Lanes along x for a construct / reconstruct wave-tile: enough 4-wide quads
-// to cover nx (no idle lanes on narrow fields), at least one chunk row.
-uint32_t choose_lx(int rank, uint64_t nx)
+// Waves along x in a construct / reconstruct workgroup tile: enough to cover
+// nx (narrow fields stack the waves along y instead).
+uint32_t choose_wx(int rank, uint64_t nx)
 {
-    if (rank == 1) return 64;
-    const uint32_t minlx = rank == 2 ? 4u : 2u;
-    const uint32_t want = p2ceil((uint32_t)std::min<uint64_t>((nx + 3) / 4, 64));
-    return std::max(minlx, std::min(64u, want));
+    if (rank == 1) return 1;
+    const uint64_t wave_x = rank == 2 ? 64 : 32;
+    const uint32_t want = p2ceil((uint32_t)std::min<uint64_t>((nx + wave_x - 1) / wave_x, 4));
+    return std::max(1u, std::min(4u, want));
 }
 
 struct Geo {
     int rank;
     uint64_t nx, ny, nz, n;
-    uint32_t lx, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
+    uint32_t wx, xs, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
     uint32_t n_seg, range_units, ow_units, n_hch, hwg_units, hdwg_units, n_rt;
 };
 
-Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc, uint32_t lx_override)
+Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc, uint32_t wx_override)
 {
     Geo g = {};
     g.rank = rank;
     g.nx = dims[0], g.ny = dims[1], g.nz = dims[2];
     g.n = g.nx * g.ny * g.nz;
-    g.lx = lx_override ? lx_override : choose_lx(rank, g.nx);
+    g.wx = wx_override ? wx_override : choose_wx(rank, g.nx);
     if (rank == 1) {
+        g.xs = 256;
         g.nxb = 1, g.nyb = 1, g.nzb = 1;
         g.n_wave_tiles = cdiv(g.n, 1024);
+        g.wg_tiles = cdiv(g.n_wave_tiles, kWavesPerBlock);
         g.n_seg = cdiv(g.n, 256);
     } else {
-        const uint32_t xs = 4 * g.lx, G = kWave / g.lx;
-        const uint32_t cy = rank == 2 ? 16 : 8, cz = rank == 2 ? 1 : 8;
-        g.nxb = cdiv(g.nx, xs);
-        g.nyb = cdiv(g.ny, (uint64_t)cy * G);
-        g.nzb = cdiv(g.nz, cz);
-        g.n_wave_tiles = g.nxb * g.nyb * g.nzb;
+        const uint32_t wy = kWavesPerBlock / g.wx;
+        const uint32_t wave_x = rank == 2 ? 64 : 32, wave_y = rank == 2 ? 16 : 8;
+        g.xs = wave_x * g.wx;
+        g.nxb = cdiv(g.nx, g.xs);
+        g.nyb = cdiv(g.ny, (uint64_t)wave_y * wy);
+        g.nzb = rank == 3 ? cdiv(g.nz, 8) : 1;
+        g.n_wave_tiles = 0;
+        g.wg_tiles = g.nxb * g.nyb * g.nzb;
         g.n_seg = (uint32_t)(g.nz * g.ny * g.nxb);
     }
-    g.wg_tiles = cdiv(g.n_wave_tiles, kWavesPerBlock);
     g.range_units = cdiv(g.n, kRangeUnit);
     g.ow_units = outlier_write_units(g.n_seg);
     g.n_hch = cdiv(g.n, hc);
@@ -168,6 +171,7 @@ struct Batch {
         bool vec;
         int first, count;
         uint32_t wg_tiles;
+        uint32_t blocks;  // construction grid
     };
     std::vector<Group> groups;
     uint32_t tot_range = 0, tot_seg = 0, tot_ow = 0, tot_hch = 0, tot_hwg = 0, tot_hdwg = 0,
@@ -200,7 +204,7 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
         const Geo& g = geo[idx[k]];
         const bool v = vec[idx[k]];
         if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v)
-            B.groups.push_back({g.rank, v, k, 0, 0});
+            B.groups.push_back({g.rank, v, k, 0, 0, 0});
         Batch::Group& G = B.groups.back();
         FieldDesc& d = B.fd[k];
         d.wg_base = G.wg_tiles;
@@ -216,6 +220,11 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
         d.rt_base = B.tot_rt, d.n_rt = g.n_rt, B.tot_rt += g.n_rt;
         B.max_rle_units = std::max(B.max_rle_units, cdiv(g.n, kBlock));
     }
+    for (auto& G : B.groups) {
+        G.blocks = std::min(G.wg_tiles, kConstructBlocks);
+        for (int k = G.first; k < G.first + G.count; ++k)
+            B.fd[k].hrows = std::min(B.fd[k].wg_tiles, G.blocks);
+    }
 }
 
 void fill_geometry(FieldDesc& d, const Geo& g, bool vec)
@@ -223,7 +232,8 @@ void fill_geometry(FieldDesc& d, const Geo& g, bool vec)
     d.n = g.n;
     d.nx = (uint32_t)g.nx, d.ny = (uint32_t)g.ny, d.nz = (uint32_t)g.nz;
     d.rank = g.rank;
-    d.lx = g.lx;
+    d.wx = g.wx;
+    d.xs = g.xs;
     d.nxb = g.nxb, d.nyb = g.nyb, d.nzb = g.nzb;
     d.n_wave_tiles = g.n_wave_tiles;
     d.vec = vec ? 1u : 0u;
@@ -278,7 +288,7 @@ void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P
         d.dsc = bp.take<int32_t>(4 * g.n);
         d.rstart = (uint32_t*)d.dsc;  // used only after the outliers are written
         d.hist = bp.take<uint32_t>(4ull * P.n_bins);
-        d.hpart = bp.take<uint32_t>(4ull * P.n_bins * g.wg_tiles);
+        d.hpart = bp.take<uint32_t>(4ull * P.n_bins * d.hrows);
         d.rpart = bp.take<uint32_t>(12ull * g.range_units);
         d.code = bp.take<uint64_t>(8ull * P.n_bins);
         d.len = bp.take<uint8_t>(P.n_bins);
@@ -335,7 +345,7 @@ int enqueue_compress(Batch& B, const Params& P, hipStream_t s, Timer& T, bool de
     HIP_TRY(launch_params(B.d_fd, nf, s));
     T.mark("construct");
     for (const auto& G : B.groups)
-        HIP_TRY(launch_construct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, P.n_bins,
+        HIP_TRY(launch_construct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, P.n_bins,
                                  B.d_seg, s));
     T.mark("hist_reduce");
     HIP_TRY(launch_hist_reduce(B.d_fd, nf, P.n_bins, s));

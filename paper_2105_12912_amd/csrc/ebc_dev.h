@@ -36,14 +36,25 @@ __device__ __forceinline__ void st_nt_f4(EBC_G float* p, f32x4 v)
     __builtin_nontemporal_store(v, (EBC_G f32x4*)p);
 }
 
-// Value of lane (l - 1) within a 16-lane DPP row; lane 0 of each row reads 0.
-__device__ __forceinline__ int dpp_shr1(int v)
+// Value of lane (l - K) within a 16-lane DPP row; lanes with l % 16 < K read 0.
+template <int K>
+__device__ __forceinline__ int dpp_shr(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);
+    return __builtin_amdgcn_update_dpp(0, v, 0x110 + K, 0xF, 0xF, true);
 }
-__device__ __forceinline__ int dpp_shr2(int v)
+template <int K>
+__device__ __forceinline__ uint32_t dpp_shr_u(uint32_t v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);
+    return (uint32_t)dpp_shr<K>((int)v);
+}
+
+// Keeps a DPP move as an instruction of its own.  Folded into a following
+// subtraction, it became v_subrev_u32_dpp, which returned the negated
+// difference on gfx950; additions and masks fold correctly.
+__device__ __forceinline__ int dpp_keep(int v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)

@@ -24,7 +24,7 @@ hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s);
 hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
-                            uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s);
+                            uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s);
 hipError_t launch_hist_reduce(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s);
 
 // codebook

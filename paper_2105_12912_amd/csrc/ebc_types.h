@@ -29,6 +29,8 @@ constexpr uint32_t kMaxBins = 4096;         // n_bins this GPU path implements
 constexpr uint32_t kMaxHc = 4096;           // Huffman chunk symbols implemented
 constexpr uint32_t kRangeUnit = 16384;      // elements per value-range work unit
 constexpr uint32_t kRleTile = 4096;         // elements per RLE work unit
+constexpr uint32_t kPersistentBlocks = 1024; // grid size of the persistent (grid-stride) kernels
+constexpr uint32_t kConstructBlocks = 2048;  // construction grid: 8 workgroups per CU
 constexpr int kLutBits = 12;                // Huffman decode table width (bits looked up at once)
 constexpr int kMaxDecodeLen = 60;
 constexpr int kLongLens = 16;              // long-code lengths compared in registers           // longest code the decoder accepts (N < 2^32 gives <= 46)
@@ -74,10 +76,13 @@ struct FieldDesc {
     int32_t eb_mode;
     int32_t codec_req;
     double eb;
-    // construct / reconstruct wave-tile geometry
-    uint32_t lx;             // lanes along x (each lane owns 4 consecutive x)
-    uint32_t nxb, nyb, nzb;  // wave-tile grid
-    uint32_t n_wave_tiles;
+    // construct / reconstruct tiling.  2D/3D: a workgroup tile is wx waves
+    // along x by 4/wx along y; a wave covers 64 x 16 (2D, four 16x16 chunks)
+    // or 32 x 8 x 8 (3D, four 8x8x8 chunks).  1D: a wave covers four chunks.
+    uint32_t wx;             // waves along x in a workgroup tile (1, 2 or 4)
+    uint32_t xs;             // x extent of a workgroup tile = outlier segment length
+    uint32_t nxb, nyb, nzb;  // workgroup-tile grid (2D/3D)
+    uint32_t n_wave_tiles;   // 1D wave tiles
     uint32_t vec;            // 1: rows 16-byte aligned, quads never straddle rows
     // buffers (device)
     const EBC_G float* in;   // compress input
@@ -87,7 +92,8 @@ struct FieldDesc {
     EBC_G uint16_t* q;       // quant-codes, n
     EBC_G int32_t* dsc;      // outlier delta scratch, n (dense, sparsely written)
     EBC_G uint32_t* hist;    // n_bins
-    EBC_G uint32_t* hpart;   // wg_tiles * n_bins partial histograms
+    EBC_G uint32_t* hpart;   // hrows * n_bins partial histograms
+    uint32_t hrows;          // construction workgroups visiting this field
     EBC_G uint32_t* rpart;   // range partials: 3 words per range unit
     EBC_G uint64_t* code;    // n_bins packed codewords: (len << 56) | code
     EBC_G uint8_t* len;      // n_bins code lengths

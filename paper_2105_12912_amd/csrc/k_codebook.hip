@@ -123,33 +123,94 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
         if (threadIdx.x == 0) dy->status = ST_ERR_ARCHIVE;
         return;
     }
-    // two-queue merge (one lane; inherently sequential)
-    if (threadIdx.x == 0 && m > 1) {
-        uint32_t li = 0, ih = 0, ni = 0;
-        uint32_t lw = (uint32_t)(keys[0] >> 16);
-        for (uint32_t k = 0; k + 1 < m; ++k) {
-            uint32_t pick[2];
-            uint32_t w = 0;
-#pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                if (li < m && (ih == ni || lw <= iw[ih])) {
-                    pick[t] = li;
-                    w += lw;
-                    ++li;
-                    lw = li < m ? (uint32_t)(keys[li] >> 16) : 0xFFFFFFFFu;
-                } else {
-                    pick[t] = m + ih;
-                    w += iw[ih];
-                    ++ih;
-                }
+    // Two-queue merge in parallel rounds.  Let t be the weight of the next
+    // internal node (sum of the two smallest available items).  Every
+    // available item of weight <= t is picked before that node and before
+    // any later one (ties: leaf before internal node, older internal node
+    // before newer), so all of them can be paired in merged order at once;
+    // an odd one out waits for the next round.  This reproduces the sequential
+    // two-queue picks exactly.
+    __shared__ uint32_t s_li, s_ih, s_ni, s_t;
+    if (threadIdx.x == 0) s_li = 0, s_ih = 0, s_ni = 0;
+    __syncthreads();
+    while (m > 1) {
+        const uint32_t li = s_li, ih = s_ih, ni = s_ni;
+        if (ni + 1 >= m) break;
+        if (threadIdx.x == 0) {
+            uint32_t a = li, b = ih, t = 0;
+            for (int k = 0; k < 2; ++k) {
+                const uint32_t lw = a < m ? (uint32_t)(keys[a] >> 16) : 0xFFFFFFFFu;
+                if (a < m && (b == ni || lw <= iw[b])) t += lw, ++a;
+                else t += iw[b], ++b;
             }
-            iw[ni] = w;
-            parent[pick[0]] = (uint16_t)(m + ni);
-            parent[pick[1]] = (uint16_t)(m + ni);
-            ++ni;
+            s_t = t;
         }
-        parent[2 * m - 2] = (uint16_t)(2 * m - 2);  // the root points to itself
+        __syncthreads();
+        const uint32_t t = s_t;
+        // available leaves / internal nodes of weight <= t (both lists sorted)
+        uint32_t cl = 0, ci = 0;
+        for (uint32_t base = li;; base += kBlock) {
+            const uint32_t i = base + threadIdx.x;
+            const int c = __syncthreads_count(i < m && (uint32_t)(keys[i] >> 16) <= t);
+            cl += c;
+            if (c < kBlock) break;
+        }
+        for (uint32_t base = ih;; base += kBlock) {
+            const uint32_t j = base + threadIdx.x;
+            const int c = __syncthreads_count(j < ni && iw[j] <= t);
+            ci += c;
+            if (c < kBlock) break;
+        }
+        const uint32_t np = (cl + ci) / 2;
+        for (uint32_t k = threadIdx.x; k < np; k += kBlock) iw[ni + k] = 0;
+        __syncthreads();
+        // merged position of every item, then parent and weight of its pair
+        for (uint32_t i = threadIdx.x; i < cl; i += kBlock) {
+            const uint32_t wi = (uint32_t)(keys[li + i] >> 16);
+            uint32_t a = 0, b = ci;  // internal nodes lighter than the leaf
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if (iw[ih + mid] < wi) a = mid + 1;
+                else b = mid;
+            }
+            const uint32_t pos = i + a;
+            if (pos < 2 * np) {
+                parent[li + i] = (uint16_t)(m + ni + pos / 2);
+                atomicAdd(&iw[ni + pos / 2], wi);
+            }
+        }
+        for (uint32_t j = threadIdx.x; j < ci; j += kBlock) {
+            const uint32_t wj = iw[ih + j];
+            uint32_t a = 0, b = cl;  // leaves not heavier than the node
+            while (a < b) {
+                const uint32_t mid = (a + b) >> 1;
+                if ((uint32_t)(keys[li + mid] >> 16) <= wj) a = mid + 1;
+                else b = mid;
+            }
+            const uint32_t pos = j + a;
+            if (pos < 2 * np) {
+                parent[m + ih + j] = (uint16_t)(m + ni + pos / 2);
+                atomicAdd(&iw[ni + pos / 2], wj);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t dl = cl, di = ci;
+            if ((cl + ci) & 1) {
+                // the last item in merged order stays: an internal node comes
+                // after a leaf of equal weight
+                bool last_is_leaf;
+                if (ci == 0) last_is_leaf = true;
+                else if (cl == 0) last_is_leaf = false;
+                else last_is_leaf = (uint32_t)(keys[li + cl - 1] >> 16) > iw[ih + ci - 1];
+                if (last_is_leaf) --dl;
+                else --di;
+            }
+            s_li = li + dl, s_ih = ih + di, s_ni = ni + np;
+        }
+        __syncthreads();
     }
+    if (threadIdx.x == 0 && m > 1) parent[2 * m - 2] = (uint16_t)(2 * m - 2);  // the root points to itself
     __syncthreads();
     // depths by pointer jumping over nodes 0 .. 2m-2 (depth <= 64 < 2^7)
     const uint32_t nn = m > 1 ? 2 * m - 1 : 1;

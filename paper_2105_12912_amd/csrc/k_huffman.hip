@@ -44,98 +44,115 @@ __device__ __forceinline__ void load_syms(const EBC_G uint16_t* __restrict__ q, 
     }
 }
 
+// Both encode kernels are persistent: a workgroup walks groups of
+// huff_cpw(hc) chunks with a grid stride and reloads the code table in LDS
+// only when it moves to another field.
 template <uint32_t S>
-__global__ __launch_bounds__(kBlock) void k_huff_bits(const FieldDesc* __restrict__ F, int nf, uint32_t* __restrict__ wcnt)
+__global__ __launch_bounds__(kBlock) void k_huff_bits(const FieldDesc* __restrict__ F, int nf,
+                                                      uint32_t* __restrict__ wcnt, uint32_t units)
 {
     __shared__ uint8_t len_s[kMaxBins];
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
-    for (uint32_t s = threadIdx.x; s < fd.n_bins; s += blockDim.x) len_s[s] = fd.len[s];
-    __syncthreads();
-    const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (c >= fd.n_hch) return;
-    const uint32_t hc = fd.hc;
-    const uint64_t lo = (uint64_t)c * hc + (uint64_t)lane_id() * S;
-    uint16_t sym[S];
-    load_syms<S>(fd.q, lo, fd.n, sym);
-    uint32_t bits = 0;
+    int cur = -1;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const EBC_G FieldDyn* dy = fd.dyn;
+        if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) continue;
+        if (f != cur) {
+            __syncthreads();
+            for (uint32_t s = threadIdx.x; s < fd.n_bins; s += blockDim.x) len_s[s] = fd.len[s];
+            __syncthreads();
+            cur = f;
+        }
+        const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
+        if (c >= fd.n_hch) continue;
+        const uint64_t lo = (uint64_t)c * fd.hc + (uint64_t)lane_id() * S;
+        uint16_t sym[S];
+        load_syms<S>(fd.q, lo, fd.n, sym);
+        uint32_t bits = 0;
 #pragma unroll
-    for (uint32_t k = 0; k < S; ++k)
-        if (lo + k < fd.n) bits += len_s[sym[k]];
-    bits = wave_sum_u32(bits);
-    if (lane_id() == 0) {
-        fd.hbits[c] = bits;
-        wcnt[fd.hch_base + c] = (bits + 31) / 32;
+        for (uint32_t k = 0; k < S; ++k)
+            if (lo + k < fd.n) bits += len_s[sym[k]];
+        bits = wave_sum_u32(bits);
+        if (lane_id() == 0) {
+            fd.hbits[c] = bits;
+            wcnt[fd.hch_base + c] = (bits + 31) / 32;
+        }
+    }
+}
+
+// append the low `take` (<= 32) bits of v to a window that starts on a word
+// boundary; full words are ORed into the chunk's LDS word buffer
+__device__ __forceinline__ void put_bits(uint64_t& acc, uint32_t& nacc, uint32_t& w, uint32_t* wbuf,
+                                         uint64_t v, uint32_t take)
+{
+    acc |= v << (64 - nacc - take);
+    nacc += take;
+    if (nacc >= 32) {
+        atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
+        ++w;
+        acc <<= 32;
+        nacc -= 32;
     }
 }
 
 template <uint32_t S>
 __global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restrict__ F, int nf,
-                             const uint32_t* __restrict__ woff)
+                                                       const uint32_t* __restrict__ woff,
+                                                       uint32_t units)
 {
     extern __shared__ uint64_t lds64[];
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
-    const uint32_t nb = fd.n_bins, hc = fd.hc;
-    uint64_t* code_s = lds64;
-    uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
-    for (uint32_t s = threadIdx.x; s < nb; s += blockDim.x) code_s[s] = fd.code[s];
-    const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const bool live = c < fd.n_hch;
-    const uint32_t cbits = live ? fd.hbits[c] : 0u;
-    const uint32_t nw = (cbits + 31) / 32;
-    for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
-    __syncthreads();
-    if (live) {
-        const uint64_t lo = (uint64_t)c * hc + (uint64_t)lane_id() * S;
-        uint16_t sym[S];
-        load_syms<S>(fd.q, lo, fd.n, sym);
-        uint32_t mybits = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < S; ++k)
-            if (lo + k < fd.n) mybits += (uint32_t)(code_s[sym[k]] >> 56);
-        const uint32_t b0 = wave_incl_scan_u32(mybits) - mybits;
-        // accumulate into a 64-bit window that always starts on a word boundary
-        uint32_t w = b0 >> 5;
-        uint32_t nacc = b0 & 31;
-        uint64_t acc = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < S; ++k) {
-            if (lo + k >= fd.n) continue;
-            const uint64_t e = code_s[sym[k]];
-            const uint32_t L = (uint32_t)(e >> 56);
-            const uint64_t cw = e & ((1ull << 56) - 1);
-            // emit in pieces of at most 32 bits: high part first
-            uint32_t rem = L;
-            while (rem) {
-                const uint32_t take = rem > 32 ? rem - 32 : rem;
-                const uint64_t piece = (cw >> (rem - take)) & ((1ull << take) - 1);
-                acc |= piece << (64 - nacc - take);
-                nacc += take;
-                rem -= take;
-                if (nacc >= 32) {
-                    atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
-                    ++w;
-                    acc <<= 32;
-                    nacc -= 32;
-                }
-            }
+    int cur = -1;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const EBC_G FieldDyn* dy = fd.dyn;
+        if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) continue;
+        const uint32_t nb = fd.n_bins, hc = fd.hc;
+        uint64_t* code_s = lds64;
+        uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
+        __syncthreads();  // previous chunk's words are out of the buffers
+        if (f != cur) {
+            for (uint32_t s = threadIdx.x; s < nb; s += blockDim.x) code_s[s] = fd.code[s];
+            cur = f;
         }
-        if (nacc) atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
-    }
-    __syncthreads();
-    if (live) {
-        EBC_G uint8_t* arc = fd.arc;
-        const uint32_t wo = woff[fd.hch_base + c] - woff[fd.hch_base];
-        EBC_G uint32_t* dst = (EBC_G uint32_t*)(arc + dy->off_words) + wo;
-        for (uint32_t i = lane_id(); i < nw; i += kWave) dst[i] = wbuf[i];
-        if (lane_id() == 0) ((EBC_G uint32_t*)(arc + dy->off_bits))[c] = cbits;
+        const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
+        const bool live = c < fd.n_hch;
+        const uint32_t cbits = live ? fd.hbits[c] : 0u;
+        const uint32_t nw = (cbits + 31) / 32;
+        for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
+        __syncthreads();
+        if (live) {
+            const uint64_t lo = (uint64_t)c * hc + (uint64_t)lane_id() * S;
+            uint16_t sym[S];
+            load_syms<S>(fd.q, lo, fd.n, sym);
+            uint32_t mybits = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < S; ++k)
+                if (lo + k < fd.n) mybits += (uint32_t)(code_s[sym[k]] >> 56);
+            const uint32_t b0 = wave_incl_scan_u32(mybits) - mybits;
+            uint32_t w = b0 >> 5, nacc = b0 & 31;
+            uint64_t acc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < S; ++k) {
+                if (lo + k >= fd.n) continue;
+                const uint64_t e = code_s[sym[k]];
+                const uint32_t L = (uint32_t)(e >> 56);
+                const uint64_t cw = e & ((1ull << 56) - 1);
+                if (L > 32) put_bits(acc, nacc, w, wbuf, cw >> 32, L - 32);  // rare long code
+                const uint32_t low = L > 32 ? 32u : L;
+                put_bits(acc, nacc, w, wbuf, cw & (low == 32 ? 0xFFFFFFFFull : ((1ull << low) - 1)), low);
+            }
+            if (nacc) atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
+        }
+        __syncthreads();
+        if (live) {
+            EBC_G uint8_t* arc = fd.arc;
+            const uint32_t wo = woff[fd.hch_base + c] - woff[fd.hch_base];
+            EBC_G uint32_t* dst = (EBC_G uint32_t*)(arc + dy->off_words) + wo;
+            for (uint32_t i = lane_id(); i < nw; i += kWave) dst[i] = wbuf[i];
+            if (lane_id() == 0) ((EBC_G uint32_t*)(arc + dy->off_bits))[c] = cbits;
+        }
     }
 }
 
@@ -461,11 +478,15 @@ hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, 
     return hipGetLastError();
 }
 
+// persistent grid: enough workgroups to fill the device several times over
+static uint32_t persistent_grid(uint32_t units) { return units < kPersistentBlocks ? units : kPersistentBlocks; }
+
 hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t* wcnt,
                             hipStream_t s)
 {
     if (!units) return hipSuccess;
-    EBC_HC_DISPATCH(k_huff_bits, dim3(units), dim3(kWave * huff_cpw(hc)), 0, s, F, nf, wcnt)
+    EBC_HC_DISPATCH(k_huff_bits, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)), 0, s, F, nf,
+                    wcnt, units)
     return hipGetLastError();
 }
 
@@ -473,8 +494,8 @@ hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s)
 {
     if (!units) return hipSuccess;
-    EBC_HC_DISPATCH(k_huff_write, dim3(units), dim3(kWave * huff_cpw(hc)),
-                    huff_write_lds_bytes(n_bins, hc), s, F, nf, woff)
+    EBC_HC_DISPATCH(k_huff_write, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)),
+                    huff_write_lds_bytes(n_bins, hc), s, F, nf, woff, units)
     return hipGetLastError();
 }
 

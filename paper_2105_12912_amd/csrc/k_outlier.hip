@@ -26,7 +26,7 @@ __device__ __forceinline__ void seg_range(const FieldDesc& fd, uint32_t s, uint6
         a = (uint64_t)s * 256;
         b = min(a + 256, fd.n);
     } else {
-        const uint32_t xs = 4 * fd.lx;
+        const uint32_t xs = fd.xs;
         const uint64_t row = s / fd.nxb;
         const uint32_t xb = s % fd.nxb;
         a = row * fd.nx + (uint64_t)xb * xs;

@@ -10,9 +10,14 @@
 //
 // Lorenzo difference as separable backward differences: with zero outside the
 // chunk, d - p = Dz Dy Dx d, where Dx v(x) = v(x) - v(x-1) (v(-1) = 0 at a
-// chunk start), and likewise for y and z.  A lane owns four consecutive x and
-// walks y (and z) sequentially, so Dy and Dz are register-only; Dx needs one
-// value from the lane on its left (DPP row shift).
+// chunk start), and likewise for y and z.  A lane owns four consecutive x.
+// 2D: lane = 16 xq + y, so the 16 rows of a 16x16 chunk are the 16 lanes of a
+// DPP row (Dy is one row shift) and Dx takes the left quad from lane - 16;
+// a wave walks four chunks along x.  3D: lane = 8 xq + y covers 32 x by 8 y,
+// Dy is a row shift by 1, Dx by 8, and the wave walks the 8 z-planes of its
+// chunks keeping Dy Dx of the previous plane in registers for Dz.  1D: a wave
+// covers four 256-long chunks.  Every load and store is a 16-byte quad per
+// lane; each quad is read and written once.
 #include "ebc_dev.h"
 #include "ebc_launch.h"
 
@@ -231,46 +236,34 @@ __device__ __forceinline__ uint32_t postquant4(const int32_t dl[4], int nvalid, 
     return om;
 }
 
-// Outliers of one row segment, summed over the LX lanes of this lane's group.
-__device__ __forceinline__ uint32_t group_count(uint32_t om, int lx, int g)
+// Outliers of one row among the lanes of that row: `rowmask` selects the
+// lanes holding the row, `om` holds this lane's 4-bit outlier mask.
+__device__ __forceinline__ uint32_t row_count(uint32_t om, uint64_t rowmask)
 {
     const uint64_t any = ballot(om != 0);
     if (any == 0) return 0;
     uint32_t cnt = 0;
-    const uint64_t gmask = lx == 64 ? ~0ull : (((1ull << lx) - 1) << (g * lx));
 #pragma unroll
-    for (int k = 0; k < 4; ++k) cnt += __popcll(ballot((om >> k) & 1u) & gmask);
+    for (int k = 0; k < 4; ++k) cnt += __popcll(ballot((om >> k) & 1u) & rowmask);
     return cnt;
 }
 
+// One workgroup tile: quantise, record outliers, count codes into the LDS
+// histogram and outlier counts per row segment into `s_cnt` (2D/3D).
 template <int RANK, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restrict__ F, int nf,
-                                                      uint32_t* __restrict__ seg_cnt)
+__device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl, QuantCtx& qc,
+                                               uint32_t* sh_hist, uint32_t* s_cnt,
+                                               uint32_t* __restrict__ segs)
 {
-    extern __shared__ uint32_t sh_hist[];
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
-    const uint32_t nb = fd.n_bins;
-    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh_hist[b] = 0;
-    __syncthreads();
-
-    QuantCtx qc;
-    qc.inv = dy->inv;
-    qc.r = (int32_t)(nb / 2);
-    qc.center = 0;
     const int l = lane_id();
-    const uint32_t wt = (t - fd.wg_base) * kWavesPerBlock + threadIdx.x / kWave;
+    const int w = threadIdx.x / kWave;
     const EBC_G float* __restrict__ in = fd.in;
     EBC_G uint16_t* __restrict__ qo = fd.q;
     EBC_G int32_t* __restrict__ dsc = fd.dsc;
-    uint32_t* __restrict__ segs = seg_cnt + fd.seg_base;
-
-    if (wt < fd.n_wave_tiles) {
-        if (RANK == 1) {
-            // wave-tile: 4 chunks of 256; lane owns x = c*256 + 4*l + k
+    if (RANK == 1) {
+        // wave tile: 4 chunks of 256; lane owns x = c*256 + 4*l + k
+        const uint32_t wt = tl * kWavesPerBlock + w;
+        if (wt < fd.n_wave_tiles) {
             const uint64_t n = fd.n;
             float v[4][4];
 #pragma unroll
@@ -293,79 +286,176 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
                 const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
                 if (VEC && nv == 4) store_codes<true>(qo, i0, 4, code);
                 else store_codes<false>(qo, i0, nv, code);
-                const uint32_t cnt = group_count(om, 64, 0);
+                const uint32_t cnt = row_count(om, ~0ull);
                 const uint64_t seg = (uint64_t)wt * 4 + c;
                 if (l == 0 && seg < fd.n_seg) segs[seg] = cnt;
             }
-        } else {
-            const int lx = (int)fd.lx;
-            const int xl = l % lx, g = l / lx;
-            const uint32_t nxb = fd.nxb, nyb = fd.nyb;
-            const uint32_t xb = wt % nxb;
-            const uint32_t yb = (wt / nxb) % nyb;
-            const uint32_t zb = wt / (nxb * nyb);
-            const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
-            const uint32_t x0 = xb * 4u * lx + 4u * xl;
+        }
+    } else {
+        // workgroup tile: wx waves along x by wy along y
+        const uint32_t wx = fd.wx, wy = kWavesPerBlock / wx;
+        const uint32_t wxi = w % wx, wyi = w / wx;
+        const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+        const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+        const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+        if (RANK == 3) {
+            // lane = 8 * xq + y: y-neighbour at lane - 1, x-neighbour at lane - 8
+            const uint32_t y = l & 7, xq = l >> 3;
+            const uint32_t x0 = xb * fd.xs + wxi * 32 + 4 * xq;
+            const uint32_t yy = yb * 8 * wy + wyi * 8 + y;
+            const uint32_t z0 = zb * 8;
             const int nv_x = x0 >= nx ? 0 : (int)min<uint32_t>(4, nx - x0);
-            // chunk-row of x: 16 elements (4 lanes) in 2D, 8 elements (2 lanes) in 3D
-            const bool x_first = RANK == 2 ? (xl % 4) == 0 : (xl % 2) == 0;
-            constexpr int CY = RANK == 2 ? 16 : 8;
-            constexpr int CZ = RANK == 2 ? 1 : 8;
-            const uint32_t y0 = yb * (uint32_t)(CY * (kWave / lx)) + (uint32_t)(CY * g);
-            const uint32_t z0 = zb * CZ;
-            int32_t fprev[CY][4];
-#pragma unroll
-            for (int j = 0; j < CY; ++j)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) fprev[j][k] = 0;
-            for (int iz = 0; iz < CZ; ++iz) {
-                const uint32_t z = z0 + iz;
-                float v[CY][4];
-#pragma unroll
-                for (int j = 0; j < CY; ++j) {
-                    const uint32_t y = y0 + j;
-                    const bool rowok = y < ny && z < nz;
-                    const uint64_t i0 = ((uint64_t)z * ny + y) * nx + x0;
-                    load_quad<VEC>(in, i0, rowok ? nv_x : 0, v[j]);
-                }
-                int32_t eprev[4] = {0, 0, 0, 0};
-#pragma unroll
-                for (int j = 0; j < CY; ++j) {
-                    const uint32_t y = y0 + j;
-                    const bool rowok = y < ny && z < nz;
-                    const int nv = rowok ? nv_x : 0;
-                    const uint64_t i0 = ((uint64_t)z * ny + y) * nx + x0;
-                    int32_t d[4], e[4], dl[4];
-                    prequant4(v[j], qc.inv, d);
-                    int left = dpp_shr1(d[3]);
-                    if (x_first) left = 0;
-                    e[0] = d[0] - left, e[1] = d[1] - d[0], e[2] = d[2] - d[1], e[3] = d[3] - d[2];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int32_t fy = e[k] - eprev[k];  // Dy Dx d
-                        eprev[k] = e[k];
-                        if (RANK == 3) {
-                            dl[k] = fy - fprev[j][k];  // Dz Dy Dx d
-                            fprev[j][k] = fy;
-                        } else {
-                            dl[k] = fy;
-                        }
-                    }
-                    uint32_t code[4];
-                    const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
-                    store_codes<VEC>(qo, i0, nv, code);
-                    const uint32_t cnt = group_count(om, lx, g);
-                    if (xl == 0 && rowok) segs[((uint64_t)z * ny + y) * nxb + xb] = cnt;
-                }
+            const uint64_t rowmask = 0x0101010101010101ull << y;
+            int32_t fprev[4] = {0, 0, 0, 0};
+            float v[4], vn[4];
+            {
+                const bool ok = yy < ny && z0 < nz;
+                load_quad<VEC>(in, ((uint64_t)z0 * ny + yy) * nx + x0, ok ? nv_x : 0, v);
             }
+            for (int iz = 0; iz < 8; ++iz) {
+                const uint32_t z = z0 + iz;
+                const bool rowok = yy < ny && z < nz;
+                const int nv = rowok ? nv_x : 0;
+                const uint64_t i0 = ((uint64_t)z * ny + yy) * nx + x0;
+                if (iz < 7) {  // next plane in flight while this one is processed
+                    const bool okn = yy < ny && z + 1 < nz;
+                    load_quad<VEC>(in, i0 + (uint64_t)ny * nx, okn ? nv_x : 0, vn);
+                }
+                int32_t d[4], e[4], dl[4];
+                prequant4(v, qc.inv, d);
+                int left = dpp_shr<8>(d[3]);
+                if ((xq & 1) == 0) left = 0;  // x chunk boundary
+                e[0] = d[0] - left, e[1] = d[1] - d[0], e[2] = d[2] - d[1], e[3] = d[3] - d[2];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    int up = dpp_keep(dpp_shr<1>(e[k]));
+                    if (y == 0) up = 0;  // y chunk boundary
+                    const int32_t fy = e[k] - up;   // Dy Dx d
+                    dl[k] = fy - fprev[k];          // Dz Dy Dx d
+                    fprev[k] = fy;
+                }
+                uint32_t code[4];
+                const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
+                store_codes<VEC>(qo, i0, nv, code);
+                const uint32_t cnt = row_count(om, rowmask);
+                if (xq == 0 && cnt) atomicAdd(&s_cnt[wyi * 64 + iz * 8 + y], cnt);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = vn[k];
+            }
+        } else {
+            // lane = 16 * xq + y: y-neighbour at lane - 1 (same DPP row),
+            // x-neighbour at lane - 16; four 16x16 chunks along x per wave
+            const uint32_t y = l & 15, xq = l >> 4;
+            const uint32_t yy = yb * 16 * wy + wyi * 16 + y;
+            const uint64_t rowmask = 0x0001000100010001ull << y;
+            const bool yok = yy < ny;
+            uint32_t rowcnt = 0;
+            float v[4], vn[4];
+            {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 4 * xq;
+                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
+                load_quad<VEC>(in, (uint64_t)yy * nx + x0, nv, v);
+            }
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * c + 4 * xq;
+                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
+                const uint64_t i0 = (uint64_t)yy * nx + x0;
+                if (c < 3) {
+                    const uint32_t x1 = x0 + 16;
+                    const int nv1 = (!yok || x1 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x1);
+                    load_quad<VEC>(in, i0 + 16, nv1, vn);
+                }
+                int32_t d[4], dl[4];
+                prequant4(v, qc.inv, d);
+                int left = __shfl_up(d[3], 16);
+                if (xq == 0) left = 0;  // x chunk boundary
+                int32_t e[4] = {d[0] - left, d[1] - d[0], d[2] - d[1], d[3] - d[2]};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dl[k] = e[k] - dpp_keep(dpp_shr<1>(e[k]));  // y = 0 reads 0
+                uint32_t code[4];
+                const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
+                store_codes<VEC>(qo, i0, nv, code);
+                rowcnt += row_count(om, rowmask);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) v[k] = vn[k];
+            }
+            if (xq == 0 && rowcnt) atomicAdd(&s_cnt[wyi * 16 + y], rowcnt);
         }
     }
-    // centre-bin counts: wave reduction, then one LDS add per wave
+}
+
+// Flush the LDS histogram of field `fd` into its partial row for this
+// workgroup and clear it.  Row (b - wg_base) mod G is unique per workgroup b
+// of the grid G among those that visit the field.
+__device__ __forceinline__ void flush_hist(const FieldDesc& fd, QuantCtx& qc, uint32_t* sh_hist)
+{
     const uint32_t cs = wave_sum_u32(qc.center);
-    if (l == 0 && cs) atomicAdd(&sh_hist[qc.r], cs);
+    qc.center = 0;
+    if (lane_id() == 0 && cs) atomicAdd(&sh_hist[qc.r], cs);
     __syncthreads();
-    EBC_G uint32_t* hp = fd.hpart + (uint64_t)(t - fd.wg_base) * nb;
-    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) hp[b] = sh_hist[b];
+    const uint32_t G = gridDim.x, nb = fd.n_bins;
+    const uint32_t row = (blockIdx.x + G - fd.wg_base % G) % G;
+    EBC_G uint32_t* hp = fd.hpart + (uint64_t)row * nb;
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
+        hp[b] = sh_hist[b];
+        sh_hist[b] = 0;
+    }
+    __syncthreads();
+}
+
+// Persistent over the workgroup tiles of one (rank, layout) group: the grid
+// strides over the tiles, so each workgroup visits every field in one run of
+// consecutive tiles and flushes one partial histogram per field it visits.
+template <int RANK, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restrict__ F, int nf,
+                                                      uint32_t n_tiles, uint32_t* __restrict__ seg_cnt)
+{
+    extern __shared__ uint32_t sh_hist[];
+    __shared__ uint32_t s_cnt[2][kWavesPerBlock * 64];  // outliers per row, double-buffered
+    const uint32_t nb = F[0].n_bins;
+    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh_hist[b] = 0;
+    s_cnt[0][threadIdx.x] = 0;
+    s_cnt[1][threadIdx.x] = 0;
+    __syncthreads();
+    QuantCtx qc;
+    qc.center = 0;
+    int cur = -1, par = 0;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const EBC_G FieldDyn* dy = fd.dyn;
+        if (dy->status != ST_OK || dy->codec == ARC_CONST) continue;  // uniform over the workgroup
+        if (f != cur) {
+            if (cur >= 0) flush_hist(F[cur], qc, sh_hist);
+            cur = f;
+            qc.inv = dy->inv;
+            qc.r = (int32_t)(nb / 2);
+        }
+        const uint32_t tl = t - fd.wg_base;
+        uint32_t* cnt = s_cnt[par];
+        construct_tile<RANK, VEC>(fd, tl, qc, sh_hist, cnt, seg_cnt + fd.seg_base);
+        if (RANK >= 2) {
+            __syncthreads();
+            // one outlier count per row segment of this tile; the buffer is
+            // cleared for the tile after next
+            const uint32_t wx = fd.wx, wy = kWavesPerBlock / wx;
+            const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+            const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+            const uint32_t rows = RANK == 3 ? 64 : 16;  // rows per wave-row of the tile
+            uint32_t* segs = seg_cnt + fd.seg_base;
+            const uint32_t r = threadIdx.x;
+            if (r < wy * rows) {
+                const uint32_t wyi = r / rows, rr = r % rows;
+                uint32_t z, yy;
+                if (RANK == 3) z = zb * 8 + rr / 8, yy = yb * 8 * wy + wyi * 8 + rr % 8;
+                else z = 0, yy = yb * 16 * wy + wyi * 16 + rr;
+                if (z < fd.nz && yy < fd.ny) segs[((uint64_t)z * fd.ny + yy) * nxb + xb] = cnt[r];
+            }
+            cnt[r] = 0;
+            par ^= 1;
+        }
+    }
+    if (cur >= 0) flush_hist(F[cur], qc, sh_hist);
 }
 
 // ------------------------------------------------------ histogram reduce
@@ -380,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restr
     if (b >= fd.n_bins) return;
     const uint32_t nb = fd.n_bins;
     uint32_t s = 0;
-    for (uint32_t r = blockIdx.y; r < fd.wg_tiles; r += kHistSplit) s += fd.hpart[(uint64_t)r * nb + b];
+    for (uint32_t r = blockIdx.y; r < fd.hrows; r += kHistSplit) s += fd.hpart[(uint64_t)r * nb + b];
     if (s) atomicAdd(&fd.hist[b], s);
 }
 
@@ -399,20 +489,20 @@ hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s)
 }
 
 hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
-                            uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s)
+                            uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s)
 {
     if (wg_tiles == 0) return hipSuccess;
     const size_t sh = (size_t)n_bins * sizeof(uint32_t);
-    const dim3 g(wg_tiles), b(kBlock);
+    const dim3 g(blocks), b(kBlock);
     if (rank == 1) {
-        if (vec) hipLaunchKernelGGL((k_construct<1, true>), g, b, sh, s, F, nf, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<1, false>), g, b, sh, s, F, nf, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<1, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<1, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     } else if (rank == 2) {
-        if (vec) hipLaunchKernelGGL((k_construct<2, true>), g, b, sh, s, F, nf, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<2, false>), g, b, sh, s, F, nf, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<2, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<2, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     } else {
-        if (vec) hipLaunchKernelGGL((k_construct<3, true>), g, b, sh, s, F, nf, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<3, false>), g, b, sh, s, F, nf, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<3, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<3, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     }
     return hipGetLastError();
 }

@@ -6,12 +6,13 @@
 // chunk, and the N-D sum splits into one-axis passes (x, then y, then z;
 // Algorithm 1, decompression half).  Output = d * (2 eb) rounded once to fp32.
 //
-// Mapping (same wave-tiles as construction): a lane owns four consecutive x.
-// The x pass is a within-lane prefix plus the total of the lanes to its left
-// inside the chunk row (DPP row shifts: 2 lanes per 8-wide 3D row, 4 lanes per
-// 16-wide 2D row, a full-wave scan for the 256-long 1D chunk).  The y and z
-// passes are sequential in registers: each lane walks its chunk column, so
-// the partial sums never leave the register file.  Integer sums wrap modulo
+// Mapping (same tiles and lane layout as construction): a lane owns four
+// consecutive x.  The x pass is a within-lane prefix plus the totals of the
+// quads to its left in the chunk row (one DPP row shift in 3D, two lane
+// shuffles in 2D, a full-wave scan for the 256-long 1D chunk).  The y pass is
+// a scan across the lanes of a chunk column with DPP row shifts (8 lanes in
+// 3D, the 16 lanes of a DPP row in 2D); the z pass is a running sum in
+// registers as the wave walks the chunk's planes.  Integer sums wrap modulo
 // 2^32 exactly as the CPU recurrence truncated to int32 does.
 #include "ebc_dev.h"
 #include "ebc_launch.h"
@@ -79,7 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
     const EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const int l = lane_id();
-    const uint32_t wt = (t - fd.wg_base) * kWavesPerBlock + threadIdx.x / kWave;
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t tl = t - fd.wg_base;
     const int32_t r = (int32_t)(fd.n_bins / 2);
     const double ebx2 = dy->ebx2;
     const EBC_G uint16_t* __restrict__ q = fd.q;
@@ -87,8 +89,9 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
     EBC_G float* __restrict__ out = fd.outf;
     uint32_t zeros = 0;
 
-    if (wt < fd.n_wave_tiles) {
-        if (RANK == 1) {
+    if (RANK == 1) {
+        const uint32_t wt = tl * kWavesPerBlock + w;
+        if (wt < fd.n_wave_tiles) {
             const uint64_t n = fd.n;
             uint32_t c[4][4];
 #pragma unroll
@@ -114,82 +117,109 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
                 if (VEC && nv == 4) store_quad<true>(out, i0, 4, v);
                 else store_quad<false>(out, i0, nv, v);
             }
-        } else {
-            const int lx = (int)fd.lx;
-            const int xl = l % lx, g = l / lx;
-            const uint32_t nxb = fd.nxb, nyb = fd.nyb;
-            const uint32_t xb = wt % nxb;
-            const uint32_t yb = (wt / nxb) % nyb;
-            const uint32_t zb = wt / (nxb * nyb);
-            const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
-            const uint32_t x0 = xb * 4u * lx + 4u * xl;
+        }
+    } else {
+        const uint32_t wx = fd.wx, wy = kWavesPerBlock / wx;
+        const uint32_t wxi = w % wx, wyi = w / wx;
+        const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+        const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+        const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+        if (RANK == 3) {
+            // lane = 8 * xq + y, one z-plane of an 8x8x8 chunk pair per step
+            const uint32_t y = l & 7, xq = l >> 3;
+            const uint32_t x0 = xb * fd.xs + wxi * 32 + 4 * xq;
+            const uint32_t yy = yb * 8 * wy + wyi * 8 + y;
+            const uint32_t z0 = zb * 8;
             const int nv_x = x0 >= nx ? 0 : (int)min<uint32_t>(4, nx - x0);
-            constexpr int CY = RANK == 2 ? 16 : 8;
-            constexpr int CZ = RANK == 2 ? 1 : 8;
-            const uint32_t y0 = yb * (uint32_t)(CY * (kWave / lx)) + (uint32_t)(CY * g);
-            const uint32_t z0 = zb * CZ;
-            uint32_t zprev[CY][4];
-#pragma unroll
-            for (int j = 0; j < CY; ++j)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) zprev[j][k] = 0;
-            for (int iz = 0; iz < CZ; ++iz) {
+            uint32_t zprev[4] = {0, 0, 0, 0};
+            uint32_t c[4], cn[4];
+            load_codes<VEC>(q, ((uint64_t)z0 * ny + yy) * nx + x0, (yy < ny && z0 < nz) ? nv_x : 0, c);
+            for (int iz = 0; iz < 8; ++iz) {
                 const uint32_t z = z0 + iz;
-                uint32_t c[CY][4];
+                const int nv = (yy < ny && z < nz) ? nv_x : 0;
+                const uint64_t i0 = ((uint64_t)z * ny + yy) * nx + x0;
+                if (iz < 7) load_codes<VEC>(q, i0 + (uint64_t)ny * nx, (yy < ny && z + 1 < nz) ? nv_x : 0, cn);
+                uint32_t s[4];
+                fuse4(c, nv, r, dsc, i0, s, zeros);
+                // x pass: within the quad, then the quad to the left in the chunk
+                s[1] += s[0], s[2] += s[1], s[3] += s[2];
+                uint32_t left = dpp_shr_u<8>(s[3]);
+                if ((xq & 1) == 0) left = 0;
 #pragma unroll
-                for (int j = 0; j < CY; ++j) {
-                    const uint32_t y = y0 + j;
-                    const bool rowok = y < ny && z < nz;
-                    const uint64_t i0 = ((uint64_t)z * ny + y) * nx + x0;
-                    load_codes<VEC>(q, i0, rowok ? nv_x : 0, c[j]);
+                for (int k = 0; k < 4; ++k) s[k] += left;
+                // y pass: inclusive scan over the 8 lanes of the chunk column
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    uint32_t a = dpp_shr_u<1>(s[k]);
+                    s[k] += y >= 1 ? a : 0u;
+                    a = dpp_shr_u<2>(s[k]);
+                    s[k] += y >= 2 ? a : 0u;
+                    a = dpp_shr_u<4>(s[k]);
+                    s[k] += y >= 4 ? a : 0u;
+                    // z pass: running sum over the planes of the chunk
+                    s[k] += zprev[k];
+                    zprev[k] = s[k];
                 }
-                uint32_t yprev[4] = {0, 0, 0, 0};
+                float v[4];
+                dequant4(s, ebx2, v);
+                store_quad<VEC>(out, i0, nv, v);
 #pragma unroll
-                for (int j = 0; j < CY; ++j) {
-                    const uint32_t y = y0 + j;
-                    const bool rowok = y < ny && z < nz;
-                    const int nv = rowok ? nv_x : 0;
-                    const uint64_t i0 = ((uint64_t)z * ny + y) * nx + x0;
-                    uint32_t s[4];
-                    fuse4(c[j], nv, r, dsc, i0, s, zeros);
-                    // x pass: within the lane, then the lanes to the left in the chunk row
-                    s[1] += s[0], s[2] += s[1], s[3] += s[2];
-                    uint32_t left;
-                    if (RANK == 3) {
-                        left = (uint32_t)dpp_shr1((int)s[3]);
-                        if ((xl & 1) == 0) left = 0;
-                    } else {
-                        uint32_t a = (uint32_t)dpp_shr1((int)s[3]);
-                        if ((xl & 3) == 0) a = 0;
-                        uint32_t inc = s[3] + a;  // inclusive over 2 lanes
-                        uint32_t b = (uint32_t)dpp_shr2((int)inc);
-                        if ((xl & 3) < 2) b = 0;
-                        inc += b;                 // inclusive over the 4-lane row
-                        left = inc - s[3];
-                    }
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        s[k] += left;
-                        s[k] += yprev[k];  // y pass
-                        yprev[k] = s[k];
-                        if (RANK == 3) {
-                            s[k] += zprev[j][k];  // z pass
-                            zprev[j][k] = s[k];
-                        }
-                    }
-                    float v[4];
-                    dequant4(s, ebx2, v);
-                    store_quad<VEC>(out, i0, nv, v);
+                for (int k = 0; k < 4; ++k) c[k] = cn[k];
+            }
+        } else {
+            // lane = 16 * xq + y, four 16x16 chunks along x per wave
+            const uint32_t y = l & 15, xq = l >> 4;
+            const uint32_t yy = yb * 16 * wy + wyi * 16 + y;
+            const bool yok = yy < ny;
+            uint32_t c[4], cn[4];
+            {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 4 * xq;
+                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
+                load_codes<VEC>(q, (uint64_t)yy * nx + x0, nv, c);
+            }
+            for (int ch = 0; ch < 4; ++ch) {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * ch + 4 * xq;
+                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
+                const uint64_t i0 = (uint64_t)yy * nx + x0;
+                if (ch < 3) {
+                    const uint32_t x1 = x0 + 16;
+                    const int nv1 = (!yok || x1 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x1);
+                    load_codes<VEC>(q, i0 + 16, nv1, cn);
                 }
+                uint32_t s[4];
+                fuse4(c, nv, r, dsc, i0, s, zeros);
+                // x pass: within the quad, then over the 4 quads of the chunk row
+                s[1] += s[0], s[2] += s[1], s[3] += s[2];
+                const uint32_t tot = s[3];
+                uint32_t inc = tot;
+                uint32_t a = (uint32_t)__shfl_up((int)inc, 16);
+                inc += xq >= 1 ? a : 0u;
+                a = (uint32_t)__shfl_up((int)inc, 32);
+                inc += xq >= 2 ? a : 0u;
+                const uint32_t left = inc - tot;
+                // y pass: the 16 rows of a chunk are the 16 lanes of a DPP row
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    s[k] += left;
+                    s[k] += dpp_shr_u<1>(s[k]);
+                    s[k] += dpp_shr_u<2>(s[k]);
+                    s[k] += dpp_shr_u<4>(s[k]);
+                    s[k] += dpp_shr_u<8>(s[k]);
+                }
+                float v[4];
+                dequant4(s, ebx2, v);
+                store_quad<VEC>(out, i0, nv, v);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) c[k] = cn[k];
             }
         }
     }
     // zero codes seen by this workgroup (checked against the outlier count)
     const uint32_t zs = wave_sum_u32(zeros);
     __shared__ uint32_t s_z[kWavesPerBlock];
-    if (l == 0) s_z[threadIdx.x / kWave] = zs;
+    if (l == 0) s_z[w] = zs;
     __syncthreads();
-    if (threadIdx.x == 0) fd.zpart[t - fd.wg_base] = s_z[0] + s_z[1] + s_z[2] + s_z[3];
+    if (threadIdx.x == 0) fd.zpart[tl] = s_z[0] + s_z[1] + s_z[2] + s_z[3];
 }
 
 // decompression epilogue: the code-0 count must equal the outlier count

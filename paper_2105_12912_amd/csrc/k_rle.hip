@@ -71,42 +71,45 @@ __device__ __forceinline__ uint32_t block_excl_scan_rle(uint32_t v, uint32_t* to
     return off + inc - v;
 }
 
+// Both encode passes are persistent (grid stride over the tiles).
 __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restrict__ F, int nf,
-                                                      uint32_t* __restrict__ rcnt)
+                                                      uint32_t* __restrict__ rcnt, uint32_t units)
 {
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
-    uint16_t c[kRleItems];
-    const uint32_t flags = run_flags(fd, (uint64_t)(t - fd.rt_base) * kRleTile, c);
-    uint32_t tot;
-    block_excl_scan_rle(__popc(flags), &tot);
-    if (threadIdx.x == 0) rcnt[t] = tot;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const EBC_G FieldDyn* dy = fd.dyn;
+        if (dy->status != ST_OK || dy->codec != ARC_RLE) continue;
+        uint16_t c[kRleItems];
+        const uint32_t flags = run_flags(fd, (uint64_t)(t - fd.rt_base) * kRleTile, c);
+        uint32_t tot;
+        block_excl_scan_rle(__popc(flags), &tot);
+        if (threadIdx.x == 0) rcnt[t] = tot;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restrict__ F, int nf,
-                                                      const uint32_t* __restrict__ roff)
+                                                      const uint32_t* __restrict__ roff, uint32_t units)
 {
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
-    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
-    uint16_t c[kRleItems];
-    const uint32_t flags = run_flags(fd, lo, c);
-    uint32_t tot;
-    uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
-    EBC_G uint16_t* val = (EBC_G uint16_t*)(fd.arc + kHdr);
-    const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const EBC_G FieldDyn* dy = fd.dyn;
+        if (dy->status != ST_OK || dy->codec != ARC_RLE) continue;
+        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+        uint16_t c[kRleItems];
+        const uint32_t flags = run_flags(fd, lo, c);
+        uint32_t tot;
+        uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
+        EBC_G uint16_t* val = (EBC_G uint16_t*)(fd.arc + kHdr);
+        const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
 #pragma unroll
-    for (int k = 0; k < kRleItems; ++k) {
-        if (flags & (1u << k)) {
-            val[pos] = c[k];
-            fd.rstart[pos] = (uint32_t)(i0 + k);
-            ++pos;
+        for (int k = 0; k < kRleItems; ++k) {
+            if (flags & (1u << k)) {
+                val[pos] = c[k];
+                fd.rstart[pos] = (uint32_t)(i0 + k);
+                ++pos;
+            }
         }
     }
 }
@@ -228,7 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
 hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t* rcnt, hipStream_t s)
 {
     if (!units) return hipSuccess;
-    hipLaunchKernelGGL(k_rle_count, dim3(units), dim3(kBlock), 0, s, F, nf, rcnt);
+    const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
+    hipLaunchKernelGGL(k_rle_count, dim3(g), dim3(kBlock), 0, s, F, nf, rcnt, units);
     return hipGetLastError();
 }
 
@@ -236,7 +240,8 @@ hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const ui
                             hipStream_t s)
 {
     if (!units) return hipSuccess;
-    hipLaunchKernelGGL(k_rle_write, dim3(units), dim3(kBlock), 0, s, F, nf, roff);
+    const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
+    hipLaunchKernelGGL(k_rle_write, dim3(g), dim3(kBlock), 0, s, F, nf, roff, units);
     return hipGetLastError();
 }
 

@@ -17,7 +17,6 @@ timed on the host (single thread) on the same field.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -58,32 +57,27 @@ def algo_bytes(stage: str, n: int, o: int, w: int, r: int, n_bins: int) -> float
     return table.get(stage)
 
 
-def kernel_source_hash(paths) -> str:
-    h = hashlib.sha256()
-    for p in paths:
-        h.update(open(os.path.join(ROOT, p), "rb").read())
-    return h.hexdigest()[:16]
+# stage name -> kernel name in rocprofv3 output
+STAGE_KERNEL = {"construct": "k_construct", "reconstruct": "k_reconstruct",
+                "huffman_decode": "k_huff_decode", "encode_write": "k_huff_write",
+                "encode_count": "k_huff_bits", "range": "k_range"}
 
 
-KERNEL_SOURCES = {
-    "construct": ["paper_2105_12912_amd/csrc/k_quant.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
-    "reconstruct": ["paper_2105_12912_amd/csrc/k_recon.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
-    "huffman_decode": ["paper_2105_12912_amd/csrc/k_huffman.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
-    "encode_write": ["paper_2105_12912_amd/csrc/k_huffman.hip", "paper_2105_12912_amd/csrc/ebc_dev.h"],
-}
+def traffic_from_profiles(stage: str, workload: str):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed counter summary, if it was taken on the current kernel source."""
+    from paper_2105_12912_amd import prof_summary
 
-
-def traffic_from_profiles(kernel: str, workload: str):
-    """HBM bytes per launch from a committed counter summary, if it was taken
-    on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path) or kernel not in KERNEL_SOURCES:
+    kname = STAGE_KERNEL.get(stage)
+    if not kname or not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path)).get(f"{kernel}/{workload}")
-    except Exception:
+        with open(path) as f:
+            rec = json.load(f)[workload]["kernels"][kname]
+    except (KeyError, ValueError, OSError):
         return None
-    if not rec or rec.get("source_hash") != kernel_source_hash(KERNEL_SOURCES[kernel]):
+    if rec.get("source_hash") != prof_summary.source_hash(kname):
         return None
     return rec.get("bytes_per_launch")
 
@@ -112,6 +106,8 @@ def main():
     ap.add_argument("--workload", default="nyx512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -123,6 +119,16 @@ def main():
     import torch
 
     from paper_2105_12912_amd import ebc, synth
+
+    if args.copy_probe:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "copies": 5}))
+        return
 
     desc, gen, eb = WORKLOADS[args.workload]
     print(f"[bench] generating {args.workload}: {desc}", file=sys.stderr, flush=True)

@@ -98,6 +98,101 @@ def cpu_baseline(x: np.ndarray, eb: float, ref_bytes: bytes | None):
     ), a, y
 
 
+def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
+    """The 64-field mixed-rank batch: one graph replay of the batched path
+    against the same fields through sequential plain calls (each of which
+    synchronises once to return its size), compress and decompress."""
+    import torch
+
+    from paper_2105_12912_amd import autotune, batch, ebc, synth
+
+    man = synth.batch_manifest()
+    print(f"[bench] generating the {len(man)}-field batch on the device", file=sys.stderr, flush=True)
+    fields = [synth.manifest_field_torch(e) for e in man]
+    torch.cuda.synchronize()
+    nbytes = sum(4 * x.numel() for x in fields)
+    table, report = [], {}
+    if autotune_on:
+        print("[bench] autotuning tile shapes", file=sys.stderr, flush=True)
+        table, report = autotune.tune(fields, eb)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        ts = []
+        for _ in range(n):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(s)
+            fn()
+            e1.record(s)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts.sort()
+        return ts[len(ts) // 2]
+
+    # plain path: one ebc_compress / ebc_decompress call per field
+    ws = ebc.Workspace(fields[0].device)
+    prm = ebc.make_params(eb)
+    outs = [torch.empty(ebc.ebc_compress_bound(x.dim(), tuple(reversed(x.shape)), prm),
+                        dtype=torch.uint8, device=x.device) for x in fields]
+    arcs = [None] * len(fields)
+
+    def plain_c():
+        for i, x in enumerate(fields):
+            arcs[i] = ebc.compress(x, eb, "rel", workspace=ws, out=outs[i])
+
+    print("[bench] batch: plain compress", file=sys.stderr, flush=True)
+    plain_c()
+    t_plain_c = timed(plain_c, reps)
+    ys = [torch.empty(x.shape, dtype=torch.float32, device=x.device) for x in fields]
+
+    def plain_d():
+        for i, a in enumerate(arcs):
+            ebc.decompress(a, out=ys[i], workspace=ws)
+
+    print("[bench] batch: plain decompress", file=sys.stderr, flush=True)
+    plain_d()
+    t_plain_d = timed(plain_d, reps)
+
+    print("[bench] batch: graph capture + replay", file=sys.stderr, flush=True)
+    B = batch.BatchCompress(fields, eb)
+    B.capture()
+    t_batch_c = timed(B.replay, reps)
+    barcs = B.archives()
+    same_c = all(a.numel() == b.numel() and torch.equal(a, b) for a, b in zip(barcs, arcs))
+    D = batch.BatchDecompress(arcs)
+    D.capture()
+    t_batch_d = timed(D.replay, reps)
+    ok_d = D.statuses() == [0] * len(arcs)
+    same_d = ok_d and all(torch.equal(u.view(torch.int32), v.view(torch.int32).reshape(u.shape))
+                          for u, v in zip(D.outs, ys))
+    gb = nbytes / 1e9
+    res = {
+        "workload": "64 fields of mixed rank (22 1D random walks 1e6-2.8e8, 21 2D GRF up to "
+                    "1800x3600, 21 3D GRF/lognormal 64^3-384^3 and 100x500x500), rel eb 1e-4",
+        "fields": len(fields), "input_bytes": nbytes,
+        "compress": {"plain_ms": round(t_plain_c, 3), "batched_ms": round(t_batch_c, 3),
+                     "plain_GBps": round(gb / (t_plain_c / 1e3), 2),
+                     "batched_GBps": round(gb / (t_batch_c / 1e3), 2),
+                     "speedup": round(t_plain_c / t_batch_c, 3)},
+        "decompress": {"plain_ms": round(t_plain_d, 3), "batched_ms": round(t_batch_d, 3),
+                       "plain_GBps": round(gb / (t_plain_d / 1e3), 2),
+                       "batched_GBps": round(gb / (t_batch_d / 1e3), 2),
+                       "speedup": round(t_plain_d / t_batch_d, 3)},
+        "batched_equals_plain": {"archives": bool(same_c), "reconstructions": bool(same_d)},
+        "compression_ratio": round(nbytes / sum(a.numel() for a in arcs), 3),
+        "autotune": {"classes": len(table),
+                     "table": [[e["rank"], e["nx_class"], e["n_class"], e["tile_wx"], e["grid"]]
+                               for e in table]},
+        "path": "batched = one HIP-graph replay of ebc_batch_*_async; plain = sequential "
+                "ebc_compress / ebc_decompress, one synchronisation each",
+    }
+    del B, D, fields, arcs, ys, outs
+    ebc.ebc_set_tuning([])
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +201,8 @@ def main():
     ap.add_argument("--workload", default="nyx512", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batched comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="batched comparison with default tiles")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -249,6 +346,10 @@ def main():
             "reconstruction_bits_equal": bool(np.array_equal(oy.view(np.uint32),
                                                              y.cpu().numpy().view(np.uint32))),
         }
+    if not args.no_batch:
+        del xd, ydev, out_buf, ws
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batched(eb, not args.no_autotune)
     print(json.dumps(result))
 
 

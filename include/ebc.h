@@ -185,6 +185,14 @@ int ebc_batch_compress_workspace_size(int n, const ebc_field* fields, const ebc_
 int ebc_batch_compress(int n, const ebc_field* fields, const ebc_params* p, ebc_result* results,
                        void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* As ebc_batch_compress without any synchronisation: d_results (device, n
+   records of 16 bytes, caller's order) receives {out_size, status, codec}
+   when the stream reaches the end of the work.  Only kernel launches are
+   enqueued, so the call can be captured into a HIP graph; host-side
+   validation errors are returned immediately and enqueue nothing. */
+int ebc_batch_compress_async(int n, const ebc_field* fields, const ebc_params* p,
+                             ebc_result* d_results, void* d_ws, uint64_t ws_bytes, void* stream);
+
 typedef struct ebc_archive_ref {
     const void* d_archive; /* device */
     uint64_t size;
@@ -197,6 +205,36 @@ int ebc_batch_decompress_workspace_size(int n, const ebc_archive_ref* refs, uint
 /* Decompress n archives; statuses (host, n entries) filled after one sync. */
 int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, void* d_ws,
                          uint64_t ws_bytes, void* stream);
+/* As ebc_batch_decompress without synchronisation: d_statuses (device, n
+   int32, caller's order) receives each field's status.  Kernel launches only
+   (graph-capturable). */
+int ebc_batch_decompress_async(int n, const ebc_archive_ref* refs, int32_t* d_statuses,
+                               void* d_ws, uint64_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------- */
+/* Tuning: tile shape and grid per (rank, shape class).  Tuning never       */
+/* changes the output bytes, only the launch geometry.                      */
+/* ---------------------------------------------------------------------- */
+typedef struct ebc_tuning_entry {
+    int32_t rank;      /* 1, 2 or 3 */
+    uint32_t nx_class; /* ceil(log2(nx)) */
+    uint32_t n_class;  /* 0: N < 2^20, 1: N < 2^24, 2: larger */
+    uint32_t tile_wx;  /* 2D/3D workgroup tile width in waves along x (1, 2 or 4); the
+                          tile is tile_wx * 64 x (4/tile_wx) * 16 in 2D and
+                          tile_wx * 32 x (4/tile_wx) * 8 x 8 in 3D; 0 = default */
+    uint32_t grid;     /* persistent construction grid in workgroups, 64..16384;
+                          0 = default (2048) */
+} ebc_tuning_entry;
+
+/* Replace the library's tuning table (n = 0 clears it).  This table is the
+   library's only global state: every later call takes one snapshot of it.
+   Calls already running are unaffected.  A workspace size obtained under one
+   table may be too small under another (the call then fails with
+   EBC_ERR_WS_TOO_SMALL; it never overruns). */
+int ebc_set_tuning(const ebc_tuning_entry* entries, int n);
+
+/* Shape class of a field, as used to look up the tuning table. */
+int ebc_shape_class(int rank, const uint64_t dims[3], uint32_t* nx_class, uint32_t* n_class);
 
 /* ---------------------------------------------------------------------- */
 /* Test / inspection entry points: stop the compression after the          */

@@ -14,6 +14,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <vector>
 
 #include "ebc.h"
@@ -50,6 +52,53 @@ inline uint32_t p2ceil(uint32_t v)
     uint32_t p = 1;
     while (p < v) p <<= 1;
     return p;
+}
+
+// ------------------------------------------------------------------ tuning
+// The only global state: a table of tile choices per (rank, shape class),
+// replaced as a whole by ebc_set_tuning.  Each API call takes one snapshot
+// (TuneScope) so that workspace sizing and planning inside the call agree.
+using TuneTable = std::vector<ebc_tuning_entry>;
+std::mutex g_tune_mu;
+std::shared_ptr<const TuneTable> g_tune;
+thread_local const TuneTable* t_tune = nullptr;
+
+struct TuneScope {
+    std::shared_ptr<const TuneTable> snap;
+    TuneScope()
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        snap = g_tune;
+        t_tune = snap.get();
+    }
+    ~TuneScope() { t_tune = nullptr; }
+};
+
+void shape_class(int rank, const uint64_t dims[3], uint32_t* nxc, uint32_t* nc)
+{
+    uint32_t c = 0;
+    while (c < 31 && (1ull << c) < dims[0]) ++c;
+    const uint64_t n = dims[0] * (rank > 1 ? dims[1] : 1) * (rank > 2 ? dims[2] : 1);
+    *nxc = c;
+    *nc = n < (1ull << 20) ? 0u : n < (1ull << 24) ? 1u : 2u;
+}
+
+struct Tune {
+    uint32_t wx, grid;
+};
+
+Tune lookup_tune(int rank, const uint64_t dims[3])
+{
+    Tune t = {0, 0};
+    if (!t_tune) return t;
+    uint32_t nxc, nc;
+    shape_class(rank, dims, &nxc, &nc);
+    for (const auto& e : *t_tune)
+        if (e.rank == rank && e.nx_class == nxc && e.n_class == nc) {
+            t.wx = e.tile_wx;
+            t.grid = e.grid;
+        }
+    return t;
 }
 
 // ------------------------------------------------------------------ params
@@ -113,16 +162,19 @@ struct Geo {
     int rank;
     uint64_t nx, ny, nz, n;
     uint32_t wx, xs, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
+    uint32_t grid;  // persistent construction grid (workgroups)
     uint32_t n_seg, range_units, ow_units, n_hch, hwg_units, hdwg_units, n_rt;
 };
 
-Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc, uint32_t wx_override)
+Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc)
 {
     Geo g = {};
     g.rank = rank;
     g.nx = dims[0], g.ny = dims[1], g.nz = dims[2];
     g.n = g.nx * g.ny * g.nz;
-    g.wx = wx_override ? wx_override : choose_wx(rank, g.nx);
+    const Tune t = lookup_tune(rank, dims);
+    g.wx = rank > 1 && t.wx ? t.wx : choose_wx(rank, g.nx);
+    g.grid = t.grid ? t.grid : kConstructBlocks;
     if (rank == 1) {
         g.xs = 256;
         g.nxb = 1, g.nyb = 1, g.nzb = 1;
@@ -221,7 +273,9 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
         B.max_rle_units = std::max(B.max_rle_units, cdiv(g.n, kBlock));
     }
     for (auto& G : B.groups) {
-        G.blocks = std::min(G.wg_tiles, kConstructBlocks);
+        uint32_t grid = 0;
+        for (int k = G.first; k < G.first + G.count; ++k) grid = std::max(grid, geo[B.order[k]].grid);
+        G.blocks = std::min(G.wg_tiles, grid);
         for (int k = G.first; k < G.first + G.count; ++k)
             B.fd[k].hrows = std::min(B.fd[k].wg_tiles, G.blocks);
     }
@@ -249,15 +303,14 @@ struct CompressIn {
     uint64_t cap;
 };
 
-void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P, uint8_t* ws,
-                   uint32_t lx_override = 0)
+void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P, uint8_t* ws)
 {
     B.nf = (int)fin.size();
     B.fd.assign(B.nf, FieldDesc{});
     std::vector<Geo> geo(B.nf);
     std::vector<bool> vec(B.nf);
     for (int i = 0; i < B.nf; ++i) {
-        geo[i] = make_geo(fin[i].rank, fin[i].dims, P.hc, lx_override);
+        geo[i] = make_geo(fin[i].rank, fin[i].dims, P.hc);
         vec[i] = aligned16(fin[i].in) && (fin[i].rank == 1 || geo[i].nx % 4 == 0);
     }
     assign_bases(B, geo, vec);
@@ -284,6 +337,7 @@ void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P
         d.arc = (uint8_t*)fin[i].out;
         d.arc_cap = fin[i].cap;
         d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
+        d.slot = (uint32_t)B.order[k];
         d.q = bp.take<uint16_t>(2 * g.n);
         d.dsc = bp.take<int32_t>(4 * g.n);
         d.rstart = (uint32_t*)d.dsc;  // used only after the outliers are written
@@ -497,8 +551,7 @@ struct DecompressIn {
     uint64_t out_elems;
 };
 
-void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws,
-                     uint32_t lx_override = 0)
+void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
 {
     B.nf = (int)din.size();
     B.fd.assign(B.nf, FieldDesc{});
@@ -506,7 +559,7 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
     std::vector<bool> vec(B.nf);
     for (int i = 0; i < B.nf; ++i) {
         const Header& H = din[i].H;
-        geo[i] = make_geo(H.rank, H.dims, H.hc, lx_override);
+        geo[i] = make_geo(H.rank, H.dims, H.hc);
         vec[i] = aligned16(din[i].out) && (H.rank == 1 || geo[i].nx % 4 == 0);
     }
     assign_bases(B, geo, vec);
@@ -568,6 +621,7 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.arc = (uint8_t*)D.arc;
         d.arc_cap = D.size;
         d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
+        d.slot = (uint32_t)B.order[k];
         d.n_out_hdr = H.n_out;
         d.n_words_hdr = H.n_words;
         d.ebx2_hdr = H.ebx2;
@@ -640,6 +694,35 @@ extern "C" {
 
 int ebc_version(void) { return EBC_VERSION; }
 
+int ebc_set_tuning(const ebc_tuning_entry* entries, int n)
+{
+    if (n < 0 || (n > 0 && !entries)) return fail(EBC_ERR_ARG, "bad tuning table");
+    auto t = std::make_shared<TuneTable>();
+    for (int i = 0; i < n; ++i) {
+        const ebc_tuning_entry& e = entries[i];
+        if (e.rank < 1 || e.rank > 3) return fail(EBC_ERR_ARG, "tuning entry %d: bad rank", i);
+        if (e.tile_wx != 0 && e.tile_wx != 1 && e.tile_wx != 2 && e.tile_wx != 4)
+            return fail(EBC_ERR_ARG, "tuning entry %d: tile_wx must be 0, 1, 2 or 4", i);
+        if (e.grid != 0 && (e.grid < 64 || e.grid > 16384))
+            return fail(EBC_ERR_ARG, "tuning entry %d: grid must be 0 or in [64, 16384]", i);
+        t->push_back(e);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (n == 0) g_tune.reset();
+    else g_tune = t;
+    return EBC_OK;
+}
+
+int ebc_shape_class(int rank, const uint64_t dims[3], uint32_t* nx_class, uint32_t* n_class)
+{
+    if (!nx_class || !n_class) return fail(EBC_ERR_ARG, "NULL argument");
+    uint64_t n;
+    int st = check_dims(rank, dims, &n);
+    if (st) return st;
+    shape_class(rank, dims, nx_class, n_class);
+    return EBC_OK;
+}
+
 const char* ebc_status_string(int status)
 {
     switch (status) {
@@ -663,6 +746,7 @@ const char* ebc_last_error(void) { return g_err; }
 
 int ebc_compress_bound(int rank, const uint64_t dims[3], const ebc_params* p, uint64_t* max_bytes)
 {
+    TuneScope tune_scope;
     Params P;
     uint64_t n;
     if (!max_bytes) return fail(EBC_ERR_ARG, "max_bytes is NULL");
@@ -682,6 +766,7 @@ int ebc_compress_bound(int rank, const uint64_t dims[3], const ebc_params* p, ui
 
 int ebc_compress_workspace_size(int rank, const uint64_t dims[3], const ebc_params* p, uint64_t* bytes)
 {
+    TuneScope tune_scope;
     Params P;
     uint64_t n;
     if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
@@ -701,6 +786,7 @@ int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const e
                  void* d_out, uint64_t out_cap, uint64_t* out_size, void* d_ws, uint64_t ws_bytes,
                  void* stream, ebc_stats* stats)
 {
+    TuneScope tune_scope;
     if (!out_size) return fail(EBC_ERR_ARG, "out_size is NULL");
     *out_size = 0;
     if (!dims) return fail(EBC_ERR_ARG, "dims is NULL");
@@ -730,6 +816,7 @@ int ebc_compress_async(const float* d_field, int rank, const uint64_t dims[3], c
                        void* d_out, uint64_t out_cap, uint64_t* d_result, void* d_ws,
                        uint64_t ws_bytes, void* stream)
 {
+    TuneScope tune_scope;
     if (!d_result || !dims) return fail(EBC_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     std::vector<CompressIn> fin(1);
@@ -767,6 +854,7 @@ int ebc_archive_info(const void* h_header, uint64_t header_bytes, int* rank, uin
 
 int ebc_decompress_workspace_size(const void* h_header, uint64_t header_bytes, uint64_t* bytes)
 {
+    TuneScope tune_scope;
     if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
     std::vector<DecompressIn> din(1);
     int st = parse_header(h_header, header_bytes, &din[0].H);
@@ -805,6 +893,7 @@ static int decompress_impl(const Header& H, const void* d_archive, uint64_t size
 int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t out_elems,
                    void* d_ws, uint64_t ws_bytes, void* stream, ebc_stats* stats)
 {
+    TuneScope tune_scope;
     hipStream_t s = (hipStream_t)stream;
     if (!d_archive) return fail(EBC_ERR_ARG, "archive is NULL");
     if (size < kHdr) return fail(EBC_ERR_ARCHIVE, "archive shorter than its header");
@@ -840,6 +929,7 @@ int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t s
                          uint64_t out_elems, void* d_ws, uint64_t ws_bytes, int32_t* d_status,
                          void* stream)
 {
+    TuneScope tune_scope;
     if (!d_status) return fail(EBC_ERR_ARG, "d_status is NULL");
     hipStream_t s = (hipStream_t)stream;
     Header H;
@@ -857,6 +947,7 @@ int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t s
 int ebc_batch_compress_workspace_size(int n, const ebc_field* fields, const ebc_params* p,
                                       uint64_t* bytes)
 {
+    TuneScope tune_scope;
     if (n <= 0 || !fields || !bytes) return fail(EBC_ERR_ARG, "bad batch arguments");
     Params P;
     int st = check_params(p, &P);
@@ -879,6 +970,7 @@ int ebc_batch_compress_workspace_size(int n, const ebc_field* fields, const ebc_
 int ebc_batch_compress(int n, const ebc_field* fields, const ebc_params* p, ebc_result* results,
                        void* d_ws, uint64_t ws_bytes, void* stream)
 {
+    TuneScope tune_scope;
     if (n <= 0 || !fields || !results) return fail(EBC_ERR_ARG, "bad batch arguments");
     hipStream_t s = (hipStream_t)stream;
     std::vector<CompressIn> fin(n);
@@ -907,6 +999,30 @@ int ebc_batch_compress(int n, const ebc_field* fields, const ebc_params* p, ebc_
     return first_err;
 }
 
+static_assert(sizeof(ebc_result) == 16, "ebc_result is written by the device as two u64 words");
+
+int ebc_batch_compress_async(int n, const ebc_field* fields, const ebc_params* p,
+                             ebc_result* d_results, void* d_ws, uint64_t ws_bytes, void* stream)
+{
+    TuneScope tune_scope;
+    if (n <= 0 || !fields || !d_results) return fail(EBC_ERR_ARG, "bad batch arguments");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(n);
+    for (int i = 0; i < n; ++i)
+        fin[i] = {fields[i].d_field, fields[i].rank,
+                  {fields[i].dims[0], fields[i].dims[1], fields[i].dims[2]}, fields[i].d_out,
+                  fields[i].out_cap};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(nullptr, s);
+    st = enqueue_compress(B, P, s, T);
+    if (st) return st;
+    HIP_TRY(launch_batch_results(B.d_fd, n, (uint64_t*)d_results, s));
+    return EBC_OK;
+}
+
 static int batch_dec_inputs(int n, const ebc_archive_ref* refs, std::vector<DecompressIn>& din)
 {
     if (n <= 0 || !refs) return fail(EBC_ERR_ARG, "bad batch arguments");
@@ -926,6 +1042,7 @@ static int batch_dec_inputs(int n, const ebc_archive_ref* refs, std::vector<Deco
 
 int ebc_batch_decompress_workspace_size(int n, const ebc_archive_ref* refs, uint64_t* bytes)
 {
+    TuneScope tune_scope;
     if (!bytes) return fail(EBC_ERR_ARG, "bytes is NULL");
     std::vector<DecompressIn> din;
     int st = batch_dec_inputs(n, refs, din);
@@ -936,11 +1053,10 @@ int ebc_batch_decompress_workspace_size(int n, const ebc_archive_ref* refs, uint
     return EBC_OK;
 }
 
-int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, void* d_ws,
-                         uint64_t ws_bytes, void* stream)
+static int batch_dec_prepare(int n, const ebc_archive_ref* refs, void* d_ws, uint64_t ws_bytes,
+                             hipStream_t s, Batch& B)
 {
-    if (!statuses || !d_ws) return fail(EBC_ERR_ARG, "NULL argument");
-    hipStream_t s = (hipStream_t)stream;
+    if (!d_ws) return fail(EBC_ERR_ARG, "workspace is NULL");
     std::vector<DecompressIn> din;
     int st = batch_dec_inputs(n, refs, din);
     if (st) return st;
@@ -952,10 +1068,19 @@ int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, 
     Batch sizing;
     plan_decompress(sizing, din, nullptr);
     if (ws_bytes < sizing.ws_bytes) return fail(EBC_ERR_WS_TOO_SMALL, "workspace too small");
-    Batch B;
     plan_decompress(B, din, (uint8_t*)d_ws);
     Timer T(nullptr, s);
-    st = enqueue_decompress(B, s, T);
+    return enqueue_decompress(B, s, T);
+}
+
+int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, void* d_ws,
+                         uint64_t ws_bytes, void* stream)
+{
+    TuneScope tune_scope;
+    if (!statuses) return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    Batch B;
+    int st = batch_dec_prepare(n, refs, d_ws, ws_bytes, s, B);
     if (st) return st;
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);
@@ -968,12 +1093,26 @@ int ebc_batch_decompress(int n, const ebc_archive_ref* refs, int32_t* statuses, 
     return first_err;
 }
 
+int ebc_batch_decompress_async(int n, const ebc_archive_ref* refs, int32_t* d_statuses, void* d_ws,
+                               uint64_t ws_bytes, void* stream)
+{
+    TuneScope tune_scope;
+    if (!d_statuses) return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    Batch B;
+    int st = batch_dec_prepare(n, refs, d_ws, ws_bytes, s, B);
+    if (st) return st;
+    HIP_TRY(launch_batch_status(B.d_fd, n, d_statuses, s));
+    return EBC_OK;
+}
+
 // ------------------------------------------------------------------ debug
 int ebc_debug_construct(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
                         uint16_t* d_q, uint32_t* d_hist, uint32_t* d_oidx, int32_t* d_oval,
                         uint64_t* n_outliers, double* ebx2, void* d_ws, uint64_t ws_bytes,
                         void* stream)
 {
+    TuneScope tune_scope;
     if (!d_q || !d_hist || !d_oidx || !d_oval || !n_outliers || !dims)
         return fail(EBC_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
@@ -1017,6 +1156,7 @@ int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int
                           uint64_t n_outliers, int rank, const uint64_t dims[3], uint32_t n_bins,
                           double ebx2, float* d_out, void* d_ws, uint64_t ws_bytes, void* stream)
 {
+    TuneScope tune_scope;
     if (!d_q || !d_out || !dims || !d_ws || (n_outliers && (!d_oidx || !d_oval)))
         return fail(EBC_ERR_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;

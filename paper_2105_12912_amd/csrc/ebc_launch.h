@@ -70,6 +70,8 @@ hipError_t launch_layout(const FieldDesc* F, int nf, const uint32_t* soff, const
 hipError_t launch_header(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_result(const FieldDesc* F, uint64_t* res, hipStream_t s);
 hipError_t launch_status(const FieldDesc* F, int32_t* st, hipStream_t s);
+hipError_t launch_batch_results(const FieldDesc* F, int nf, uint64_t* res, hipStream_t s);
+hipError_t launch_batch_status(const FieldDesc* F, int nf, int32_t* st, hipStream_t s);
 hipError_t upload_descs(const FieldDesc* host, int nf, FieldDesc* dev, hipStream_t s);
 
 }  // namespace ebc

@@ -84,6 +84,7 @@ struct FieldDesc {
     uint32_t nxb, nyb, nzb;  // workgroup-tile grid (2D/3D)
     uint32_t n_wave_tiles;   // 1D wave tiles
     uint32_t vec;            // 1: rows 16-byte aligned, quads never straddle rows
+    uint32_t slot;           // position of this field in the caller's arrays
     // buffers (device)
     const EBC_G float* in;   // compress input
     EBC_G float* outf;       // decompress output

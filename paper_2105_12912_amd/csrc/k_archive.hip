@@ -129,6 +129,26 @@ __global__ void k_status(const FieldDesc* __restrict__ F, int32_t* __restrict__ 
     *st = F[0].dyn->status;
 }
 
+// Batch result records in the caller's order: {archive bytes (0 on error),
+// status, codec} = 16 bytes per field.
+__global__ void k_batch_results(const FieldDesc* __restrict__ F, int nf, uint64_t* __restrict__ res)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nf) return;
+    const FieldDesc& fd = F[k];
+    const EBC_G FieldDyn* dy = fd.dyn;
+    uint64_t* r = res + 2ull * fd.slot;
+    r[0] = dy->status == ST_OK ? dy->total : 0ull;
+    r[1] = (uint64_t)(uint32_t)dy->status | ((uint64_t)(uint32_t)dy->codec << 32);
+}
+
+__global__ void k_batch_status(const FieldDesc* __restrict__ F, int nf, int32_t* __restrict__ st)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nf) return;
+    st[F[k].slot] = F[k].dyn->status;
+}
+
 // Upload up to kDescPerLaunch descriptors passed by value.
 __global__ void k_put_desc(DescBlob blob, FieldDesc* __restrict__ dst)
 {
@@ -158,6 +178,18 @@ hipError_t launch_result(const FieldDesc* F, uint64_t* res, hipStream_t s)
 hipError_t launch_status(const FieldDesc* F, int32_t* st, hipStream_t s)
 {
     hipLaunchKernelGGL(k_status, dim3(1), dim3(1), 0, s, F, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_results(const FieldDesc* F, int nf, uint64_t* res, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_results, dim3((nf + 63) / 64), dim3(64), 0, s, F, nf, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_status(const FieldDesc* F, int nf, int32_t* st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_status, dim3((nf + 63) / 64), dim3(64), 0, s, F, nf, st);
     return hipGetLastError();
 }
 

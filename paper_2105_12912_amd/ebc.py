@@ -65,6 +65,11 @@ class ebc_archive_ref(C.Structure):
                 ("d_out", C.c_void_p), ("out_elems", C.c_uint64)]
 
 
+class ebc_tuning_entry(C.Structure):
+    _fields_ = [("rank", C.c_int32), ("nx_class", C.c_uint32), ("n_class", C.c_uint32),
+                ("tile_wx", C.c_uint32), ("grid", C.c_uint32)]
+
+
 class EbcError(RuntimeError):
     def __init__(self, status: int, call: str):
         detail = ""
@@ -93,6 +98,10 @@ _SIGS = {
     "ebc_batch_compress": (_I32, [_I32, _P, _P, _P, _P, _U64, _P]),
     "ebc_batch_decompress_workspace_size": (_I32, [_I32, _P, _P]),
     "ebc_batch_decompress": (_I32, [_I32, _P, _P, _P, _U64, _P]),
+    "ebc_batch_compress_async": (_I32, [_I32, _P, _P, _P, _P, _U64, _P]),
+    "ebc_set_tuning": (_I32, [_P, _I32]),
+    "ebc_shape_class": (_I32, [_I32, _P, _P, _P]),
+    "ebc_batch_decompress_async": (_I32, [_I32, _P, _P, _P, _U64, _P]),
     "ebc_debug_construct": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P]),
     "ebc_debug_reconstruct": (_I32, [_P, _P, _P, _U64, _I32, _P, _U32, _F64, _P, _P, _U64, _P]),
 }
@@ -241,6 +250,33 @@ def ebc_batch_decompress(refs, d_ws, ws_bytes, stream):
     sts = (C.c_int32 * len(refs))()
     st = lib().ebc_batch_decompress(len(refs), arr, sts, d_ws, ws_bytes, stream)
     return st, list(sts)
+
+
+def ebc_batch_compress_async(fields, params, d_results, d_ws, ws_bytes, stream) -> int:
+    arr = (ebc_field * len(fields))(*fields)
+    return lib().ebc_batch_compress_async(len(fields), arr, C.byref(params), d_results, d_ws,
+                                          ws_bytes, stream)
+
+
+def ebc_batch_decompress_async(refs, d_statuses, d_ws, ws_bytes, stream) -> int:
+    arr = (ebc_archive_ref * len(refs))(*refs)
+    return lib().ebc_batch_decompress_async(len(refs), arr, d_statuses, d_ws, ws_bytes, stream)
+
+
+def ebc_set_tuning(entries) -> int:
+    """entries: iterable of dicts with rank, nx_class, n_class, tile_wx, grid."""
+    entries = list(entries)
+    arr = (ebc_tuning_entry * max(len(entries), 1))(
+        *[ebc_tuning_entry(**{k: int(e[k]) for k in ("rank", "nx_class", "n_class", "tile_wx",
+                                                       "grid")}) for e in entries])
+    return lib().ebc_set_tuning(arr if entries else None, len(entries))
+
+
+def ebc_shape_class(rank, dims):
+    """(nx_class, n_class) of a field."""
+    a, b = C.c_uint32(), C.c_uint32()
+    _check(lib().ebc_shape_class(rank, _dims3(dims), C.byref(a), C.byref(b)), "ebc_shape_class")
+    return a.value, b.value
 
 
 def ebc_debug_construct(d_field, rank, dims, params, d_q, d_hist, d_oidx, d_oval, d_ws, ws_bytes,

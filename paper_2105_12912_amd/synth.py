@@ -189,3 +189,67 @@ def request_stream(seed: int = 5, rate: float = 200.0, duration: float = 60.0,
                         n=max(1, int(nbytes // 4)),
                         eb=float(rng.choice([1e-2, 1e-3, 1e-4]))))
     return out
+
+
+# ------------------------------------------------------- device-side variants
+# The same recipes drawn with torch's generator on the GPU, for the large
+# benchmark batches (seconds instead of minutes to generate).  Same
+# definitions, a different random stream: these fields are not bit-identical
+# to the numpy ones above.
+
+def _t():
+    import torch
+    return torch
+
+
+def grf_torch(shape, beta: float = -3.0, seed: int = 0, device="cuda"):
+    """Device GRF: white N(0,1) filtered by k^(beta/2), standardised (float64)."""
+    torch = _t()
+    shape = tuple(int(s) for s in shape)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    white = torch.randn(shape, generator=g, device=device, dtype=torch.float64)
+    spec = torch.fft.rfftn(white)
+    del white
+    k2 = None
+    for ax, n in enumerate(shape):
+        if ax == len(shape) - 1:
+            f = torch.fft.rfftfreq(n, device=device, dtype=torch.float64) * n
+        else:
+            f = torch.fft.fftfreq(n, device=device, dtype=torch.float64) * n
+        sh = [1] * len(shape)
+        sh[ax] = f.numel()
+        term = (f * f).reshape(sh)
+        k2 = term if k2 is None else k2 + term
+    amp = torch.where(k2 > 0, k2.clamp(min=1e-300) ** (beta / 4.0), torch.zeros_like(k2))
+    out = torch.fft.irfftn(spec * amp, s=shape)
+    del spec
+    sd = out.std()
+    return (out - out.mean()) / (sd if float(sd) > 0 else 1.0)
+
+
+def _scale_t(a, lo=-1.0, hi=1.0):
+    amin, amax = float(a.min()), float(a.max())
+    if amax == amin:
+        return a.new_full(a.shape, lo)
+    return lo + (a - amin) * ((hi - lo) / (amax - amin))
+
+
+def manifest_field_torch(entry, device="cuda"):
+    """A batch-manifest field generated on the device (float32, contiguous)."""
+    torch = _t()
+    shape, seed, kind = entry["shape"], entry["seed"], entry["kind"]
+    if kind == "walk":
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed))
+        w = torch.randn(int(shape[0]), generator=g, device=device, dtype=torch.float64).cumsum_(0)
+        return _scale_t(w).float().contiguous()
+    gr = grf_torch(shape, -3.0, seed, device)
+    if kind == "grf":
+        return _scale_t(gr).float().contiguous()
+    flat = gr.reshape(-1)
+    kth = int(math.floor(0.40 * (flat.numel() - 1)))
+    thr = float(torch.sort(flat).values[kth])
+    out = torch.exp(1.5 * gr)
+    out[gr <= thr] = math.exp(1.5 * thr)
+    return out.float().contiguous()

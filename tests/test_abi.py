@@ -99,3 +99,36 @@ def test_workspace_grows_with_field(L):
     b = ebc.ebc_compress_workspace_size(3, (128, 128, 128), p)
     assert b > 6 * a
     assert a >= 6 * 64 ** 3
+
+
+def test_tuning_table_validation_and_shape_class(L):
+    bad = [dict(rank=4, nx_class=0, n_class=0, tile_wx=0, grid=0),
+           dict(rank=2, nx_class=0, n_class=0, tile_wx=3, grid=0),
+           dict(rank=2, nx_class=0, n_class=0, tile_wx=2, grid=10),
+           dict(rank=3, nx_class=0, n_class=0, tile_wx=2, grid=20000)]
+    for e in bad:
+        assert ebc.ebc_set_tuning([e]) == ebc.EBC_ERR_ARG
+    ok = dict(rank=3, nx_class=9, n_class=2, tile_wx=2, grid=1024)
+    assert ebc.ebc_set_tuning([ok]) == 0
+    assert ebc.ebc_set_tuning([]) == 0
+    assert ebc.ebc_shape_class(3, (512, 512, 512)) == (9, 2)
+    assert ebc.ebc_shape_class(2, (3600, 1800)) == (12, 1)
+    assert ebc.ebc_shape_class(1, (1000,)) == (10, 0)
+    assert ebc.ebc_shape_class(1, (1,)) == (0, 0)
+    with pytest.raises(ebc.EbcError):
+        ebc.ebc_shape_class(2, (5, 0))
+
+
+def test_tuning_changes_workspace_plan_not_validity(L):
+    """A tile choice changes the planned workspace (tile counts) but sizing is
+    always self-consistent; tuning is host-side state only."""
+    p = ebc.make_params(1e-4)
+    base = ebc.ebc_compress_workspace_size(3, (100, 100, 100), p)
+    nxc, nc = ebc.ebc_shape_class(3, (100, 100, 100))
+    sizes = []
+    for wx in (1, 2, 4):
+        assert ebc.ebc_set_tuning([dict(rank=3, nx_class=nxc, n_class=nc, tile_wx=wx, grid=0)]) == 0
+        sizes.append(ebc.ebc_compress_workspace_size(3, (100, 100, 100), p))
+    assert ebc.ebc_set_tuning([]) == 0
+    assert ebc.ebc_compress_workspace_size(3, (100, 100, 100), p) == base
+    assert all(s > 0 for s in sizes)

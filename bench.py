@@ -193,6 +193,41 @@ def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
     return res
 
 
+def bench_serving(seconds: float, warmup: float, rate: float = 200.0):
+    """The Poisson request stream through the continuous-batching loop."""
+    import torch
+
+    from paper_2105_12912_amd import serve, synth
+
+    n_base = 1 << 29  # 2 GiB of fp32 per base field
+    print("[bench] serving: generating six 2 GiB base fields on the device", file=sys.stderr,
+          flush=True)
+    bases = {}
+    for i, (rank, kind) in enumerate([(r, k) for r in (1, 2, 3) for k in ("grf", "lognormal")]):
+        bases[(rank, kind)] = synth.serving_base_torch(rank, kind, n_base, 500 + i)
+        torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    def make_input(spec):
+        b = bases[(spec["rank"], spec["kind"])]
+        if b.dim() == 1:
+            return b[:max(1, min(spec["n"], b.numel()))]
+        row = b[0].numel()
+        return b[:max(1, min(spec["n"] // row, b.shape[0]))]
+
+    stream = synth.request_stream(seed=5, rate=rate, duration=seconds)
+    server = serve.Server(hbm_budget=96 << 30, slots=4, max_batch=32)
+    print(f"[bench] serving: {len(stream)} requests over {seconds:.0f} s", file=sys.stderr, flush=True)
+    summary = serve.run_stream(server, stream, make_input, warmup=warmup)
+    summary.update(workload=f"Poisson {rate:.0f} req/s for {seconds:.0f} s (first {warmup:.0f} s "
+                            "not measured), sizes log-uniform 1 MB-2 GB fp32, rank 1/2/3, GRF or "
+                            "sparse lognormal, rel eb from {1e-2, 1e-3, 1e-4}, half decompress "
+                            "of earlier archives; inputs are prefix views of device-resident fields")
+    del bases, server
+    torch.cuda.empty_cache()
+    return summary
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +237,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batched comparison")
+    ap.add_argument("--serve-seconds", type=float, default=12.0,
+                    help="length of the serving stream (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true", help="batched comparison with default tiles")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (counter calibration)")
@@ -350,6 +387,8 @@ def main():
         del xd, ydev, out_buf, ws
         torch.cuda.empty_cache()
         result["batched"] = bench_batched(eb, not args.no_autotune)
+    if args.serve_seconds > 0:
+        result["serving"] = bench_serving(args.serve_seconds, min(2.0, args.serve_seconds / 4))
     print(json.dumps(result))
 
 

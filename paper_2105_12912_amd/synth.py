@@ -247,9 +247,34 @@ def manifest_field_torch(entry, device="cuda"):
     gr = grf_torch(shape, -3.0, seed, device)
     if kind == "grf":
         return _scale_t(gr).float().contiguous()
-    flat = gr.reshape(-1)
-    kth = int(math.floor(0.40 * (flat.numel() - 1)))
-    thr = float(torch.sort(flat).values[kth])
-    out = torch.exp(1.5 * gr)
-    out[gr <= thr] = math.exp(1.5 * thr)
-    return out.float().contiguous()
+    return lognormal_from_torch(gr).float().contiguous()
+
+
+def lognormal_from_torch(g, sigma: float = 1.5, background_frac: float = 0.40):
+    """exp(sigma g) with the lowest `background_frac` of g set to one constant."""
+    torch = _t()
+    flat = g.reshape(-1)
+    kth = int(math.floor(background_frac * (flat.numel() - 1)))
+    thr = float(torch.kthvalue(flat.cpu() if flat.numel() < (1 << 24) else flat, kth + 1).values)
+    out = torch.exp(sigma * g)
+    out[g <= thr] = math.exp(sigma * thr)
+    return out
+
+
+def serving_base_torch(rank: int, kind: str, n: int, seed: int, device="cuda"):
+    """A device-resident base field of about n elements for the serving stream:
+    1D (n,), 2D (n / 16384, 16384), 3D (n / 512^2, 512, 512); requests take
+    prefixes of whole rows / planes."""
+    torch = _t()
+    if rank == 1:
+        shape = (int(n),)
+    elif rank == 2:
+        shape = (max(1, int(n) // 16384), 16384)
+    else:
+        shape = (max(1, int(n) // (512 * 512)), 512, 512)
+    if rank == 1 and kind == "grf":
+        return manifest_field_torch(dict(shape=shape, seed=seed, kind="walk"), device)
+    g = grf_torch(shape, -3.0, seed, device)
+    if kind == "grf":
+        return _scale_t(g).float().contiguous()
+    return lognormal_from_torch(g).float().contiguous()

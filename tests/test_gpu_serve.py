@@ -1,0 +1,128 @@
+"""GPU: the continuous-batching request loop.
+
+Every served result must equal the same request run alone (through the plain
+single-field calls) byte for byte, and a sample must equal the CPU oracle;
+the in-flight device memory must stay within the budget; requests that
+arrive while others run must be batched and overlapped.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2105_12912_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_2105_12912_amd import ebc
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ebc.lib()
+    return ebc
+
+
+@pytest.fixture(scope="module")
+def bases():
+    """Small device-resident base fields per (rank, kind); inputs are prefix views."""
+    host = {
+        (1, "grf"): synth.random_walk_1d(1 << 20, 51),
+        (1, "lognormal"): np.exp(2.0 * synth.random_walk_1d(1 << 20, 52)).astype(np.float32),
+        (2, "grf"): synth.grf_field((512, 1024), 53),
+        (2, "lognormal"): np.exp(1.5 * synth.grf((512, 1024), -3.0, 54)).astype(np.float32),
+        (3, "grf"): synth.grf_field((64, 96, 128), 55),
+        (3, "lognormal"): synth.lognormal_3d((64, 96, 128), 56),
+    }
+    return {k: torch.from_numpy(v).cuda() for k, v in host.items()}
+
+
+def prefix(bases, spec):
+    """Whole rows / planes of a base field holding about spec['n'] elements."""
+    b = bases[(spec["rank"], spec["kind"])]
+    if b.dim() == 1:
+        return b[:max(1, min(spec["n"], b.numel()))]
+    row = b[0].numel()
+    k = max(1, min(spec["n"] // row, b.shape[0]))
+    return b[:k]
+
+
+def small_stream(seed, n, rate):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    for _ in range(n):
+        t += rng.exponential(1.0 / rate)
+        out.append(dict(t=t, op="compress" if rng.random() < 0.5 else "decompress",
+                        rank=int(rng.integers(1, 4)),
+                        kind="grf" if rng.random() < 0.5 else "lognormal",
+                        n=int(np.exp(rng.uniform(np.log(256), np.log(1 << 20)))),
+                        eb=float(rng.choice([1e-2, 1e-3, 1e-4]))))
+    return out
+
+
+def check_alone(E, r):
+    if r.op == "compress":
+        alone = E.compress(r.x, r.eb, "rel")
+        assert r.out.numel() == alone.numel() and torch.equal(r.out, alone), f"request {r.rid}"
+    else:
+        alone = E.decompress(r.archive)
+        assert torch.equal(r.out.view(torch.int32), alone.view(torch.int32)), f"request {r.rid}"
+
+
+def test_burst_is_batched_and_equals_alone(E, bases):
+    from paper_2105_12912_amd.serve import Request, Server
+
+    S = Server(hbm_budget=1 << 30, slots=3, max_batch=8)
+    specs = small_stream(61, 30, 1e9)
+    reqs = []
+    for sp in specs:  # all arrive at once: compress only (no archives yet)
+        reqs.append(S.submit(Request("compress", 0.0, x=prefix(bases, sp), eb=sp["eb"])))
+    S.drain()
+    assert all(r.status == 0 for r in reqs)
+    assert max(r.batch_size for r in reqs) > 1
+    assert S.batches < len(reqs)
+    assert S.peak_in_use <= S.budget
+    for r in reqs:
+        check_alone(E, r)
+    # a sample against the oracle
+    for r in reqs[::7]:
+        ref = O.compress(r.x.cpu().numpy(), r.eb, "rel")
+        assert r.out.cpu().numpy().tobytes() == ref
+    # the archives back through the loop as a decompress burst
+    dreqs = [S.submit(Request("decompress", 0.0, archive=r.out)) for r in reqs]
+    S.drain()
+    assert all(r.status == 0 for r in dreqs)
+    for r in dreqs:
+        check_alone(E, r)
+    for r, c in list(zip(dreqs, reqs))[::7]:
+        ref = O.decompress(c.out.cpu().numpy().tobytes())
+        np.testing.assert_array_equal(r.out.cpu().numpy().view(np.uint32).ravel(),
+                                      ref.view(np.uint32).ravel())
+
+
+def test_stream_mixed_ops_equal_alone_within_budget(E, bases):
+    from paper_2105_12912_amd.serve import Server, run_stream
+
+    budget = 48 << 20  # small: forces requests to wait for memory
+    S = Server(hbm_budget=budget, slots=3, max_batch=6)
+    stream = small_stream(62, 80, 400.0)
+    done = []
+    summary = run_stream(S, stream, lambda sp: prefix(bases, sp), on_result=done.append,
+                         keep_results=True)
+    assert summary["requests"] == len(stream)
+    assert summary["ok"] == len(stream)
+    assert summary["decompress"] > 0 and summary["compress"] > 0
+    assert S.peak_in_use <= budget
+    assert summary["p99_ms"] >= summary["p50_ms"] > 0
+    for r in done:
+        check_alone(E, r)
+
+
+def test_oversized_request_is_rejected(E, bases):
+    from paper_2105_12912_amd.serve import Request, Server
+
+    S = Server(hbm_budget=1 << 20, slots=1)
+    r = S.submit(Request("compress", 0.0, x=bases[(3, "grf")], eb=1e-3))
+    assert r.status == E.EBC_ERR_OUT_TOO_SMALL
+    assert not S.busy()

@@ -326,10 +326,18 @@ int ora_choose_rle(const uint64_t* hist, const uint8_t* len, uint32_t n_bins, ui
 /* ------------------------------------------------------------------------ */
 /* C10a: chunked Huffman encoding.  Chunks of hc symbols; each chunk starts  */
 /* on a 32-bit word; code bits are written MSB-first; bit 31 of a chunk's    */
-/* first word is its first bit; unused bits are zero.  Writes bits[c] for    */
-/* every chunk and, when words != NULL, the words in chunk order.            */
-/* Returns the total word count.                                             */
+/* first word is its first bit; unused bits are zero.  Writes the chunk      */
+/* entry bits[c] for every chunk and, when words != NULL, the words in      */
+/* chunk order.  Returns the total word count.                               */
+/*                                                                          */
+/* Chunk entry (container choice, not from the paper): the chunk's bit      */
+/* count; for hc <= 1024 the count is below 2^16 (lengths are at most 46    */
+/* for N < 2^32) and the high half holds the bit offset at which the        */
+/* chunk's symbol hc/2 starts (the bit count when the chunk is shorter), so */
+/* a decoder can start on both halves of a chunk at once.                   */
 /* ------------------------------------------------------------------------ */
+uint32_t ora_chunk_bits(uint32_t entry, uint32_t hc) { return hc <= 1024 ? entry & 0xFFFFu : entry; }
+
 uint64_t ora_huffman_encode(const uint16_t* q, uint64_t n, const uint8_t* len,
                             const uint64_t* code, uint32_t hc, uint32_t* bits, uint32_t* words)
 {
@@ -337,9 +345,13 @@ uint64_t ora_huffman_encode(const uint16_t* q, uint64_t n, const uint8_t* len,
     uint64_t wbase = 0;
     for (uint64_t c = 0; c < nch; ++c) {
         uint64_t lo = c * hc, hi = lo + hc < n ? lo + hc : n;
-        uint64_t nb = 0;
-        for (uint64_t i = lo; i < hi; ++i) nb += len[q[i]];
-        bits[c] = (uint32_t)nb;
+        uint64_t nb = 0, mid = 0;
+        for (uint64_t i = lo; i < hi; ++i) {
+            if (i == lo + hc / 2) mid = nb;
+            nb += len[q[i]];
+        }
+        if (hi - lo <= hc / 2) mid = nb;
+        bits[c] = hc <= 1024 ? (uint32_t)nb | ((uint32_t)mid << 16) : (uint32_t)nb;
         uint64_t nw = (nb + 31) / 32;
         if (words) {
             for (uint64_t w = 0; w < nw; ++w) words[wbase + w] = 0;
@@ -408,13 +420,18 @@ int ora_huffman_decode(const uint32_t* bits, const uint32_t* words, uint64_t n_w
     uint64_t wbase = 0;
     for (uint64_t c = 0; c < nch && st == ORA_OK; ++c) {
         uint64_t lo = c * hc, hi = lo + hc < n ? lo + hc : n;
-        uint64_t nb = bits[c], nw = (nb + 31) / 32;
-        if (wbase + nw > n_words) {
+        uint64_t nb = ora_chunk_bits(bits[c], hc), nw = (nb + 31) / 32;
+        uint64_t mid = hc <= 1024 ? bits[c] >> 16 : 0;
+        if (wbase + nw > n_words || (hc <= 1024 && hi - lo <= hc / 2 && mid != nb)) {
             st = ORA_ERR_ARCHIVE;
             break;
         }
         uint64_t pos = 0;
         for (uint64_t i = lo; i < hi; ++i) {
+            if (hc <= 1024 && i == lo + hc / 2 && pos != mid) {
+                st = ORA_ERR_ARCHIVE;
+                break;
+            }
             uint64_t v = 0;
             int l = 0, found = 0;
             while (l < 64) {

@@ -48,6 +48,16 @@ __device__ __forceinline__ uint32_t dpp_shr_u(uint32_t v)
     return (uint32_t)dpp_shr<K>((int)v);
 }
 
+// Workgroup-uniform read of data that no kernel writes while this one runs
+// (e.g. the per-field scalars written by earlier kernels): through the
+// constant address space it becomes a scalar load, which does not count
+// against the vector-memory counter and so never waits on loads in flight.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* kconst(const EBC_G T* p)
+{
+    return (const __attribute__((address_space(4))) T*)p;
+}
+
 // Keeps a DPP move as an instruction of its own.  Folded into a following
 // subtraction, it became v_subrev_u32_dpp, which returned the negated
 // difference on gfx950; additions and masks fold correctly.

@@ -32,8 +32,10 @@ constexpr uint32_t kRleTile = 4096;         // elements per RLE work unit
 constexpr uint32_t kPersistentBlocks = 1024; // grid size of the persistent (grid-stride) kernels
 constexpr uint32_t kConstructBlocks = 2048;  // construction grid: 8 workgroups per CU
 constexpr int kLutBits = 12;                // Huffman decode table width (bits looked up at once)
-constexpr int kMaxDecodeLen = 60;
-constexpr int kLongLens = 16;              // long-code lengths compared in registers           // longest code the decoder accepts (N < 2^32 gives <= 46)
+constexpr int kMaxDecodeLen = 60;          // longest code the decoder accepts (N < 2^32 gives <= 46)
+constexpr int kLongLens = 16;              // long-code lengths compared in registers
+constexpr uint32_t kL2Size = 2048;         // second-level decode table entries
+constexpr uint32_t kL2MaxBits = 8;         // bits a second-level table resolves at most
 
 enum : int32_t { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2 };
 enum : int32_t { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2 };
@@ -127,7 +129,10 @@ struct FieldDesc {
 // lut[p] decodes the next kLutBits stream bits p into up to three whole
 // codewords: bits 0-15/16-31/32-47 the symbols (zero when absent), 48-49 how
 // many (0 = the first codeword is longer than kLutBits), 50-55 their total
-// length, 56-59 and 60-63 the lengths of the first two.
+// length, 56-59 and 60-63 the lengths of the first two.  When the first
+// codeword is longer, bits 0-15 hold the start of this prefix's block of
+// 2^l2k entries in l2 (0xFFFF: none), indexed by the next l2k bits; an l2
+// entry is (length << 16) | symbol, or 0 for a codeword longer still.
 struct DecTab {
     uint64_t first[65];   // first code of each length
     uint64_t endv[65];    // (first[L] + count[L]) << (64 - L): a left-aligned window w holds a
@@ -135,8 +140,11 @@ struct DecTab {
     uint32_t count[65];   // codes of each length
     uint32_t offset[65];  // index of the first symbol of each length in perm
     uint32_t max_len;
+    uint32_t l2k;             // bits resolved by the second level (0: no second level)
+    uint32_t l2n;             // second-level entries in use
     uint32_t pad;
     uint64_t lut[1u << kLutBits];
+    uint32_t l2[kL2Size];
     uint16_t perm[kMaxBins];  // symbols ordered by (length, symbol)
 };
 

@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     __shared__ uint64_t first[65];
     __shared__ uint32_t offs[65];
     __shared__ int s_bad;
+    __shared__ uint32_t s_maxl;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const uint8_t* alen = fd.arc + kHdr;
@@ -349,6 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         }
         T->first[0] = 0, T->count[0] = 0, T->offset[0] = 0;
         T->max_len = maxl;
+        s_maxl = maxl;
         if (maxl == 0 || bad) dy->status = ST_ERR_ARCHIVE;
         s_bad = bad | (maxl == 0);
     }
@@ -371,31 +373,91 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     __syncthreads();
     if (threadIdx.x <= 64) {
         const uint32_t L = threadIdx.x;
-        const uint32_t maxl = T->max_len;
+        const uint32_t maxl = s_maxl;
         uint64_t endv = ~0ull;
         if (L >= 1 && L < maxl) endv = (first[L] + cntL[L]) << (64 - L);
         T->endv[L] = endv;
     }
-    // multi-symbol lookup table
+    // Multi-symbol lookup table in two steps.  t1[p]: the codeword (length
+    // <= kLutBits) that a kLutBits-bit window p starts with, by the canonical
+    // limit test, as (L << 16) | symbol, or 0.  Then each entry chains up to
+    // three t1 lookups; a window with only r valid leading bits (the rest
+    // zero) still decodes a codeword of length <= r correctly, because such a
+    // codeword depends on its own bits only.
+    __shared__ uint32_t t1[1u << kLutBits];
+    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kBlock) {
+        uint32_t e = 0;
+        for (uint32_t l = 1; l <= (uint32_t)kLutBits; ++l) {
+            const uint64_t v = p >> (kLutBits - l);
+            if (cntL[l] && v < first[l] + cntL[l]) {
+                e = (l << 16) | perm_s[offs[l] + (uint32_t)(v - first[l])];
+                break;
+            }
+        }
+        t1[p] = e;
+    }
+    __syncthreads();
+    // Second level: number the prefixes that start a longer codeword, give
+    // each a block of 2^k entries resolving the next k bits.
+    __shared__ uint16_t lslot[1u << kLutBits];
+    __shared__ uint16_t lpref[1u << kLutBits];
+    __shared__ uint32_t s_wsum[kWavesPerBlock];
+    constexpr uint32_t kPer = (1u << kLutBits) / kBlock;
+    {
+        uint32_t c = 0;
+        for (uint32_t i = 0; i < kPer; ++i) c += t1[threadIdx.x * kPer + i] == 0;
+        const uint32_t inc = wave_incl_scan_u32(c);
+        if (lane_id() == kWave - 1) s_wsum[threadIdx.x / kWave] = inc;
+        __syncthreads();
+        uint32_t base = inc - c;
+        for (uint32_t v = 0; v < threadIdx.x / kWave; ++v) base += s_wsum[v];
+        for (uint32_t i = 0; i < kPer; ++i) {
+            const uint32_t p = threadIdx.x * kPer + i;
+            if (t1[p] == 0) {
+                lslot[p] = (uint16_t)base;
+                lpref[base] = (uint16_t)p;
+                ++base;
+            } else {
+                lslot[p] = 0xFFFF;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t nlong = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    const uint32_t maxl = s_maxl;
+    uint32_t l2k = 0;
+    if (maxl > (uint32_t)kLutBits && nlong > 0) {
+        l2k = min(kL2MaxBits, maxl - (uint32_t)kLutBits);
+        while (l2k > 0 && (nlong << l2k) > kL2Size) --l2k;
+    }
+    const uint32_t l2n = l2k ? nlong << l2k : 0u;
+    for (uint32_t i = threadIdx.x; i < l2n; i += kBlock) {
+        const uint32_t p = lpref[i >> l2k];
+        const uint64_t wv = ((uint64_t)p << l2k) | (i & ((1u << l2k) - 1));  // kLutBits + l2k bits
+        uint32_t e = 0;
+        for (uint32_t l = kLutBits + 1; l <= kLutBits + l2k; ++l) {
+            const uint64_t v = wv >> (kLutBits + l2k - l);
+            if (cntL[l] && v < first[l] + cntL[l]) {
+                e = (l << 16) | perm_s[offs[l] + (uint32_t)(v - first[l])];
+                break;
+            }
+        }
+        T->l2[i] = e;
+    }
+    if (threadIdx.x == 0) T->l2k = l2k, T->l2n = l2n;
     for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kBlock) {
         uint64_t e = 0;
         uint32_t pos = 0, n = 0;
-        while (n < 3) {
-            uint32_t L = 0, sym = 0;
-            for (uint32_t l = 1; l + pos <= (uint32_t)kLutBits; ++l) {
-                const uint64_t v = (p >> (kLutBits - pos - l)) & ((1u << l) - 1);
-                if (cntL[l] && v < first[l] + cntL[l]) {
-                    L = l;
-                    sym = perm_s[offs[l] + (uint32_t)(v - first[l])];
-                    break;
-                }
-            }
-            if (!L) break;
-            e |= (uint64_t)sym << (16 * n);
+        while (n < 3 && pos < (uint32_t)kLutBits) {
+            const uint32_t v = t1[(p << pos) & ((1u << kLutBits) - 1)];
+            const uint32_t L = v >> 16;
+            if (L == 0 || L > (uint32_t)kLutBits - pos) break;
+            e |= (uint64_t)(v & 0xFFFFu) << (16 * n);
             if (n < 2) e |= (uint64_t)L << (56 + 4 * n);
             pos += L;
             ++n;
         }
+        if (n == 0) e = l2k && lslot[p] != 0xFFFF ? (uint64_t)lslot[p] << l2k : 0xFFFFull;
         e |= (uint64_t)n << 48;
         e |= (uint64_t)pos << 50;
         T->lut[p] = e;

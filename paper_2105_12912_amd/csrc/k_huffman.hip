@@ -24,23 +24,112 @@ size_t huff_write_lds_bytes(uint32_t n_bins, uint32_t hc)
     return (size_t)n_bins * 8 + (size_t)huff_cpw(hc) * 2 * hc * 4;
 }
 
-// symbols [lo, lo + S) of a chunk, S = hc / 64, owned by one lane
+// Symbols [lo, lo + S) of a chunk (S = hc / 64, owned by one lane), kept as
+// raw 16-byte blocks so that the loads can be issued one work unit ahead and
+// unpacked only when the unit is processed.
 template <uint32_t S>
-__device__ __forceinline__ void load_syms(const EBC_G uint16_t* __restrict__ q, uint64_t lo, uint64_t n,
-                                          uint16_t* out)
+struct SymRaw {
+    static constexpr uint32_t NV = S >= 8 ? S / 8 : 1;
+    uint4 v[NV];
+    __device__ __forceinline__ uint32_t at(uint32_t k) const
+    {
+        const uint4& b = v[k / 8];
+        const uint32_t h = (k % 8) / 2;
+        const uint32_t w = h == 0 ? b.x : h == 1 ? b.y : h == 2 ? b.z : b.w;
+        return (w >> (16 * (k & 1))) & 0xFFFFu;
+    }
+};
+
+template <uint32_t S>
+__device__ __forceinline__ void load_raw(const EBC_G uint16_t* __restrict__ q, uint64_t lo, uint64_t n,
+                                         SymRaw<S>& r)
 {
     if (S >= 8 && lo + S <= n) {
 #pragma unroll
-        for (uint32_t k = 0; k < S; k += 8) {
-            const uint4 t = *(const EBC_G uint4*)(q + lo + k);
-            out[k + 0] = t.x & 0xFFFF, out[k + 1] = t.x >> 16;
-            out[k + 2] = t.y & 0xFFFF, out[k + 3] = t.y >> 16;
-            out[k + 4] = t.z & 0xFFFF, out[k + 5] = t.z >> 16;
-            out[k + 6] = t.w & 0xFFFF, out[k + 7] = t.w >> 16;
-        }
-    } else {
+        for (uint32_t k = 0; k < SymRaw<S>::NV; ++k) r.v[k] = *(const EBC_G uint4*)(q + lo + 8 * k);
+    } else {  // short chunks and the field's tail: assembled here
+        uint32_t w[4 * SymRaw<S>::NV];
 #pragma unroll
-        for (uint32_t k = 0; k < S; ++k) out[k] = lo + k < n ? q[lo + k] : 0;
+        for (uint32_t k = 0; k < 4 * SymRaw<S>::NV; ++k) w[k] = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < S; ++k)
+            if (lo + k < n) w[k / 2] |= (uint32_t)q[lo + k] << (16 * (k & 1));
+#pragma unroll
+        for (uint32_t k = 0; k < SymRaw<S>::NV; ++k)
+            r.v[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+    }
+}
+
+// One encode work unit: huff_cpw(hc) chunks, one per wavefront.
+struct EncUnit {
+    int f;
+    uint32_t c;  // this wave's chunk
+    bool ok;     // field is being Huffman-coded
+};
+
+template <uint32_t S>
+__device__ __forceinline__ EncUnit enc_unit(const FieldDesc* __restrict__ F, int nf, uint32_t t)
+{
+    EncUnit u;
+    u.f = find_field<&FieldDesc::hwg_base>(F, nf, t);
+    const FieldDesc& fd = F[u.f];
+    const auto* dk = kconst(fd.dyn);
+    u.ok = dk->status == ST_OK && dk->codec == ARC_HUFFMAN;
+    // blockDim = 64 * cpw; the chunk index is wave-uniform (scalar)
+    u.c = (t - fd.hwg_base) * huff_cpw(64 * S) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    return u;
+}
+
+// For S >= 8 the loads are unconditional (a lane with nothing to load reads
+// the start of the code array instead), so every pipeline stage issues the
+// same number of loads and the compiler's wait counts never have to assume a
+// stage without them.  Symbols past the field's end are masked by the users;
+// the tail chunk's last lane may read up to 30 bytes past the code array,
+// which the workspace always follows with the outlier scratch.
+template <uint32_t S>
+__device__ __forceinline__ void enc_issue(const FieldDesc* __restrict__ F, const EncUnit& u, SymRaw<S>& r)
+{
+    const FieldDesc& fd = F[u.f];
+    const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)lane_id() * S;
+    const bool live = u.ok && u.c < fd.n_hch && lo < fd.n;
+    if (S >= 8) {
+        const EBC_G uint16_t* p = fd.q + (live ? lo : 0);
+#pragma unroll
+        for (uint32_t k = 0; k < SymRaw<S>::NV; ++k) r.v[k] = *(const EBC_G uint4*)(p + 8 * k);
+    } else if (live) {
+        load_raw<S>(fd.q, lo, fd.n, r);
+    }
+}
+
+// Grid-stride walk over the work units with the next unit's symbols in
+// flight while the current one is processed (two static buffers, so no
+// register copy ever waits on a load).  proc(unit, symbols) must treat the
+// workgroup uniformly (it may synchronise).
+template <uint32_t S, class Proc>
+__device__ __forceinline__ void enc_pipeline(const FieldDesc* __restrict__ F, int nf, uint32_t units,
+                                             Proc& proc)
+{
+    uint32_t t = blockIdx.x;
+    if (t >= units) return;
+    SymRaw<S> A, B;
+    EncUnit ua = enc_unit<S>(F, nf, t), ub;
+    enc_issue<S>(F, ua, A);
+    for (;;) {
+        // the next stage's loads are always issued (a dead unit past the end)
+        uint32_t tn = t + gridDim.x;
+        ub = enc_unit<S>(F, nf, tn < units ? tn : t);
+        if (tn >= units) ub.ok = false;
+        enc_issue<S>(F, ub, B);
+        proc(ua, A);
+        t = tn;
+        if (t >= units) break;
+        tn = t + gridDim.x;
+        ua = enc_unit<S>(F, nf, tn < units ? tn : t);
+        if (tn >= units) ua.ok = false;
+        enc_issue<S>(F, ua, A);
+        proc(ub, B);
+        t = tn;
+        if (t >= units) break;
     }
 }
 
@@ -48,37 +137,42 @@ __device__ __forceinline__ void load_syms(const EBC_G uint16_t* __restrict__ q, 
 // huff_cpw(hc) chunks with a grid stride and reloads the code table in LDS
 // only when it moves to another field.
 template <uint32_t S>
+struct BitsProc {
+    const FieldDesc* F;
+    uint32_t* wcnt;
+    uint8_t* len_s;
+    int cur;
+    __device__ __forceinline__ void operator()(const EncUnit& u, const SymRaw<S>& r)
+    {
+        if (!u.ok) return;
+        const FieldDesc& fd = F[u.f];
+        if (u.f != cur) {
+            __syncthreads();
+            for (uint32_t s = threadIdx.x; s < fd.n_bins; s += kWave * huff_cpw(64 * S)) len_s[s] = fd.len[s];
+            __syncthreads();
+            cur = u.f;
+        }
+        if (u.c >= fd.n_hch) return;
+        const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)lane_id() * S;
+        uint32_t bits = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < S; ++k)
+            if (lo + k < fd.n) bits += len_s[r.at(k)];
+        bits = wave_sum_u32(bits);
+        if (lane_id() == 0) {
+            fd.hbits[u.c] = bits;
+            wcnt[fd.hch_base + u.c] = (bits + 31) / 32;
+        }
+    }
+};
+
+template <uint32_t S>
 __global__ __launch_bounds__(kBlock) void k_huff_bits(const FieldDesc* __restrict__ F, int nf,
                                                       uint32_t* __restrict__ wcnt, uint32_t units)
 {
     __shared__ uint8_t len_s[kMaxBins];
-    int cur = -1;
-    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
-        const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
-        const FieldDesc& fd = F[f];
-        const EBC_G FieldDyn* dy = fd.dyn;
-        if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) continue;
-        if (f != cur) {
-            __syncthreads();
-            for (uint32_t s = threadIdx.x; s < fd.n_bins; s += blockDim.x) len_s[s] = fd.len[s];
-            __syncthreads();
-            cur = f;
-        }
-        const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
-        if (c >= fd.n_hch) continue;
-        const uint64_t lo = (uint64_t)c * fd.hc + (uint64_t)lane_id() * S;
-        uint16_t sym[S];
-        load_syms<S>(fd.q, lo, fd.n, sym);
-        uint32_t bits = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < S; ++k)
-            if (lo + k < fd.n) bits += len_s[sym[k]];
-        bits = wave_sum_u32(bits);
-        if (lane_id() == 0) {
-            fd.hbits[c] = bits;
-            wcnt[fd.hch_base + c] = (bits + 31) / 32;
-        }
-    }
+    BitsProc<S> proc{F, wcnt, len_s, -1};
+    enc_pipeline<S>(F, nf, units, proc);
 }
 
 // append the low `take` (<= 32) bits of v to a window that starts on a word
@@ -97,46 +191,46 @@ __device__ __forceinline__ void put_bits(uint64_t& acc, uint32_t& nacc, uint32_t
 }
 
 template <uint32_t S>
-__global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restrict__ F, int nf,
-                                                       const uint32_t* __restrict__ woff,
-                                                       uint32_t units)
-{
-    extern __shared__ uint64_t lds64[];
-    int cur = -1;
-    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
-        const int f = find_field<&FieldDesc::hwg_base>(F, nf, t);
-        const FieldDesc& fd = F[f];
-        const EBC_G FieldDyn* dy = fd.dyn;
-        if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) continue;
+struct WriteProc {
+    const FieldDesc* F;
+    const uint32_t* woff;
+    uint64_t* lds64;
+    int cur;
+    __device__ __forceinline__ void operator()(const EncUnit& u, const SymRaw<S>& r)
+    {
+        if (!u.ok) return;
+        const FieldDesc& fd = F[u.f];
+        const auto* dy = kconst(fd.dyn);
         const uint32_t nb = fd.n_bins, hc = fd.hc;
         uint64_t* code_s = lds64;
         uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
         __syncthreads();  // previous chunk's words are out of the buffers
-        if (f != cur) {
-            for (uint32_t s = threadIdx.x; s < nb; s += blockDim.x) code_s[s] = fd.code[s];
-            cur = f;
+        if (u.f != cur) {
+            for (uint32_t s = threadIdx.x; s < nb; s += kWave * huff_cpw(64 * S)) code_s[s] = fd.code[s];
+            cur = u.f;
         }
-        const uint32_t c = (t - fd.hwg_base) * (blockDim.x / kWave) + threadIdx.x / kWave;
-        const bool live = c < fd.n_hch;
-        const uint32_t cbits = live ? fd.hbits[c] : 0u;
+        const bool live = u.c < fd.n_hch;
+        const uint32_t cbits = live ? kconst(fd.hbits)[u.c] : 0u;
+        uint32_t mid = 0;
         const uint32_t nw = (cbits + 31) / 32;
         for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
         __syncthreads();
         if (live) {
-            const uint64_t lo = (uint64_t)c * hc + (uint64_t)lane_id() * S;
-            uint16_t sym[S];
-            load_syms<S>(fd.q, lo, fd.n, sym);
+            const uint64_t lo = (uint64_t)u.c * hc + (uint64_t)lane_id() * S;
             uint32_t mybits = 0;
 #pragma unroll
             for (uint32_t k = 0; k < S; ++k)
-                if (lo + k < fd.n) mybits += (uint32_t)(code_s[sym[k]] >> 56);
+                if (lo + k < fd.n) mybits += (uint32_t)(code_s[r.at(k)] >> 56);
             const uint32_t b0 = wave_incl_scan_u32(mybits) - mybits;
+            // lane 32 starts at symbol hc/2: the chunk's midpoint bit offset
+            // (its bit count when the chunk is shorter)
+            mid = (uint32_t)__shfl((int)b0, 32);
             uint32_t w = b0 >> 5, nacc = b0 & 31;
             uint64_t acc = 0;
 #pragma unroll
             for (uint32_t k = 0; k < S; ++k) {
                 if (lo + k >= fd.n) continue;
-                const uint64_t e = code_s[sym[k]];
+                const uint64_t e = code_s[r.at(k)];
                 const uint32_t L = (uint32_t)(e >> 56);
                 const uint64_t cw = e & ((1ull << 56) - 1);
                 if (L > 32) put_bits(acc, nacc, w, wbuf, cw >> 32, L - 32);  // rare long code
@@ -148,12 +242,26 @@ __global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restri
         __syncthreads();
         if (live) {
             EBC_G uint8_t* arc = fd.arc;
-            const uint32_t wo = woff[fd.hch_base + c] - woff[fd.hch_base];
+            const auto* wk = (const __attribute__((address_space(4))) uint32_t*)woff;
+            const uint32_t wo = wk[fd.hch_base + u.c] - wk[fd.hch_base];
             EBC_G uint32_t* dst = (EBC_G uint32_t*)(arc + dy->off_words) + wo;
             for (uint32_t i = lane_id(); i < nw; i += kWave) dst[i] = wbuf[i];
-            if (lane_id() == 0) ((EBC_G uint32_t*)(arc + dy->off_bits))[c] = cbits;
+            // chunk entry: bit count, and for hc <= 1024 the midpoint in the
+            // high half (counts stay below 2^16 there)
+            if (lane_id() == 0)
+                ((EBC_G uint32_t*)(arc + dy->off_bits))[u.c] = hc <= 1024 ? cbits | (mid << 16) : cbits;
         }
     }
+};
+
+template <uint32_t S>
+__global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restrict__ F, int nf,
+                                                       const uint32_t* __restrict__ woff,
+                                                       uint32_t units)
+{
+    extern __shared__ uint64_t lds64[];
+    WriteProc<S> proc{F, woff, lds64, -1};
+    enc_pipeline<S>(F, nf, units, proc);
 }
 
 // ------------------------------------------------------------- decoding
@@ -174,24 +282,27 @@ __device__ __forceinline__ uint64_t window_at(const EBC_G uint32_t* __restrict__
     return a;
 }
 
-// Per-lane ring of the chunk's 32-bit stream words in LDS.  Words reach the
-// ring in 16-byte blocks: a block is loaded into registers and written to the
-// ring at the next wave-uniform refill point, kRefillEvery iterations later,
-// so its load has long completed when it is waited for.  Bit refills then
-// read LDS; a lane that outruns its ring reads global memory directly.
-constexpr uint32_t kRingWords = 32;
+// Per-lane ring of a stream's 32-bit words in LDS, in two halves.  The next
+// half (16-byte blocks) is always in flight in registers: at a wave-uniform
+// refill point, every kRefillEvery iterations, a lane whose reader has left
+// the older half writes the loaded half there and issues the loads of the
+// following one.  A load therefore has a whole refill period to land before
+// it is waited for, and bit refills read LDS only; a lane that outruns its
+// ring (runs of very long codes) reads global memory directly.
+constexpr uint32_t kRingWords = 16;
+constexpr uint32_t kHalfWords = kRingWords / 2;
+constexpr uint32_t kHalfBlocks = kHalfWords / 4;
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: no bank conflicts across lanes
-constexpr uint32_t kRefillEvery = 4;
+constexpr uint32_t kRefillEvery = 16;             // iterations; at most 12 bits each from the table
 
 struct WordRing {
     uint32_t* ring;                        // this lane's slots in LDS
     const EBC_G uint4* __restrict__ blk;   // aligned 16-byte blocks of the stream
     const EBC_G uint32_t* __restrict__ words;
     uint32_t nw, o, nblk;  // words, offset of word 0 inside block 0, blocks
-    uint32_t rd;           // next chunk word to hand out
+    uint32_t rd;           // next stream word to hand out
     uint32_t wr;           // block-coordinate words [wr - kRingWords, wr) are in the ring
-    uint32_t jn;           // block held in `pend`
-    uint4 pend;
+    uint4 p[kHalfBlocks];  // blocks wr/4 .. wr/4 + kHalfBlocks - 1, in flight
     __device__ __forceinline__ uint4 fetch(uint32_t j) const
     {
         if (j < nblk) {
@@ -201,14 +312,19 @@ struct WordRing {
         return make_uint4(0u, 0u, 0u, 0u);
     }
     // Stream word i.  The value always comes out of the ring slot, so the
-    // common path never waits on global memory; a lane that outran the ring
-    // first copies the word into the (already consumed) slot.
+    // merge of the two paths waits on LDS only, never on the loads in flight;
+    // a lane that outran the ring first copies the word into the (consumed)
+    // slot.
     __device__ __forceinline__ uint32_t get(uint32_t i)
     {
         const uint32_t a = i + o;
         const uint32_t slot = a % kRingWords;
         if (!(a < wr && a + kRingWords >= wr)) ring[slot] = i < nw ? words[i] : 0u;
         return ring[slot];
+    }
+    __device__ __forceinline__ void put(uint32_t* d, uint4 v)
+    {
+        d[0] = v.x, d[1] = v.y, d[2] = v.z, d[3] = v.w;
     }
     __device__ __forceinline__ void init(uint32_t* r, const EBC_G uint32_t* __restrict__ w, uint32_t n)
     {
@@ -219,25 +335,25 @@ struct WordRing {
         o = (uint32_t)((a & 15u) >> 2);
         blk = (const EBC_G uint4*)(a & ~(uintptr_t)15u);
         nblk = (o + nw + 3) / 4;
-        for (uint32_t j = 0; j < kRingWords / 4; ++j) {
-            const uint4 b = fetch(j);
-            ring[4 * j + 0] = b.x, ring[4 * j + 1] = b.y, ring[4 * j + 2] = b.z, ring[4 * j + 3] = b.w;
-        }
+#pragma unroll
+        for (uint32_t j = 0; j < kRingWords / 4; ++j) put(ring + 4 * j, fetch(j));
         wr = kRingWords;
-        jn = kRingWords / 4;
-        pend = fetch(jn);
+#pragma unroll
+        for (uint32_t k = 0; k < kHalfBlocks; ++k) p[k] = fetch(kRingWords / 4 + k);
         rd = 0;
     }
     __device__ __forceinline__ uint32_t pop() { return get(rd++); }
-    // wave-uniform refill point: move the pending block in if its slots are consumed
+    // wave-uniform refill point
     __device__ __forceinline__ void refill()
     {
-        if (jn < nblk && wr + 4 <= rd + o + kRingWords) {
+        if (wr < 4 * nblk && rd + o >= wr - kHalfWords) {
             uint32_t* d = ring + (wr % kRingWords);
-            d[0] = pend.x, d[1] = pend.y, d[2] = pend.z, d[3] = pend.w;
-            wr += 4;
-            ++jn;
-            pend = fetch(jn);
+#pragma unroll
+            for (uint32_t k = 0; k < kHalfBlocks; ++k) put(d + 4 * k, p[k]);
+            wr += kHalfWords;
+            const uint32_t j = wr / 4;
+#pragma unroll
+            for (uint32_t k = 0; k < kHalfBlocks; ++k) p[k] = fetch(j + k);
         }
     }
 };
@@ -288,7 +404,7 @@ struct LongCode {
     const uint64_t* s_endv;
     const uint64_t* s_first;
     const uint32_t* s_off;
-    const uint16_t* perm;
+    const uint16_t* perm;  // global: only codewords longer than both table levels get here
     __device__ __forceinline__ uint32_t decode(uint64_t w, uint32_t& sym) const
     {
         uint32_t L = kLutBits + 1;
@@ -305,25 +421,30 @@ struct LongCode {
     }
 };
 
-__global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restrict__ F, int nf,
-                                                        const uint32_t* __restrict__ woff,
-                                                        const uint8_t* __restrict__ tabs,
-                                                        size_t tab_stride)
+// Two lanes per chunk: the chunk entry carries the bit offset of the chunk's
+// middle symbol (hc <= 1024), so lane 0 of a pair decodes the first half and
+// lane 1 the second half from that offset; lane 0 must end exactly there.
+constexpr uint32_t kDecBlock = 2 * kBlock;
+
+__global__ __launch_bounds__(kDecBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ woff,
+                   const uint8_t* __restrict__ tabs, size_t tab_stride)
 {
     __shared__ uint64_t lut[1u << kLutBits];
-    __shared__ uint16_t perm[kMaxBins];
+    __shared__ uint32_t l2s[kL2Size];
     __shared__ uint64_t s_first[65];
     __shared__ uint64_t s_endv[65];
     __shared__ uint32_t s_off[65];
-    __shared__ uint32_t s_ring[kBlock * kRingStride];
+    __shared__ uint32_t s_ring[kDecBlock * kRingStride];
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
     const DecTab* __restrict__ T = (const DecTab*)(tabs + (size_t)f * tab_stride);
-    for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kBlock) lut[i] = T->lut[i];
-    for (uint32_t i = threadIdx.x; i < fd.n_bins; i += kBlock) perm[i] = T->perm[i];
+    for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kDecBlock) lut[i] = T->lut[i];
+    const uint32_t l2k = T->l2k, l2n = T->l2n;
+    for (uint32_t i = threadIdx.x; i < l2n; i += kDecBlock) l2s[i] = T->l2[i];
     if (threadIdx.x < 65) {
         s_first[threadIdx.x] = T->first[threadIdx.x];
         s_endv[threadIdx.x] = T->endv[threadIdx.x];
@@ -334,33 +455,52 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
 #pragma unroll
     for (int k = 0; k < kLongLens; ++k) ev[k] = T->endv[kLutBits + 1 + k];
     __syncthreads();
-    const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x;
+    const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x / 2;
+    const uint32_t half = threadIdx.x & 1;
     if (c >= fd.n_hch) return;
+    const uint32_t hc = fd.hc;
+    const bool split = hc <= 1024;
     const EBC_G uint8_t* arc = fd.arc;
-    const uint32_t nbits = ((const EBC_G uint32_t*)(arc + fd.off_bits))[c];
+    const uint32_t ent = ((const EBC_G uint32_t*)(arc + fd.off_bits))[c];
+    const uint32_t nbits = split ? ent & 0xFFFFu : ent;
+    const uint32_t mid = split ? ent >> 16 : nbits;
     const uint32_t nw = (nbits + 31) / 32;
     const uint32_t wo = woff[fd.hch_base + c] - woff[fd.hch_base];
-    if ((uint64_t)wo + nw > fd.n_words_hdr) {
+    const uint64_t lo = (uint64_t)c * hc;
+    const uint32_t nsym = (uint32_t)min<uint64_t>(hc, fd.n - lo);
+    if ((uint64_t)wo + nw > fd.n_words_hdr || mid > nbits || (split && nsym <= hc / 2 && mid != nbits)) {
         atomicMin(&dy->status, ST_ERR_ARCHIVE);
         return;
     }
-    const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + wo;
-    const uint32_t hc = fd.hc;
-    const uint64_t lo = (uint64_t)c * hc;
-    const uint32_t nsym = (uint32_t)min<uint64_t>(hc, fd.n - lo);
-    EBC_G uint16_t* __restrict__ out = fd.q + lo;
+    // this lane's symbols [s0, s1) start at chunk bit b0
+    uint32_t s0 = 0, s1 = nsym, b0 = 0;
+    if (split) {
+        if (half == 0) s1 = min(hc / 2, nsym);
+        else s0 = min(hc / 2, nsym), b0 = mid;
+    } else if (half) {
+        return;
+    }
+    const uint32_t want = s1 - s0;
+    if (want == 0) return;
+    const uint32_t w0 = b0 >> 5;
+    const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + wo + w0;
+    const uint32_t nwl = nw - w0;
+    EBC_G uint16_t* __restrict__ out = fd.q + lo + s0;
     const LongCode lc{ev, maxl > kLutBits + 1 ? maxl - kLutBits - 1 : 0u, maxl,
-                      s_endv, s_first, s_off, perm};
+                      s_endv, s_first, s_off, T->perm};
 
     WordRing wr;
-    wr.init(s_ring + threadIdx.x * kRingStride, words, nw);
+    wr.init(s_ring + threadIdx.x * kRingStride, words, nwl);
     uint64_t buf = (uint64_t)wr.pop() << 32;
     buf |= wr.pop();
-    uint32_t valid = 64, pos = 0, j = 0, it = 0;
+    // positions below are relative to word w0 of the chunk
+    const uint32_t skip = b0 & 31;
+    buf <<= skip;
+    uint32_t valid = 64 - skip, pos = skip, j = 0, it = 0;
     bool bad = false;
     SymAcc acc;
     // main loop: at least three symbols left, so whole table entries are used
-    while (j + 3 <= nsym) {
+    while (j + 3 <= want) {
         if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
         if (valid < 32) {
             buf |= (uint64_t)wr.pop() << (32 - valid);
@@ -371,11 +511,18 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
         uint32_t tl = (uint32_t)(e >> 50) & 63u;
         uint64_t syms = e & 0xFFFFFFFFFFFFull;
         if (n == 0) {
-            uint32_t sym = 0;
-            uint32_t L = lc.decode(buf, sym);
+            // second level, then the canonical search for longer codewords
+            uint32_t sym = 0, L = 0;
+            const uint32_t base = (uint32_t)e & 0xFFFFu;
+            if (base != 0xFFFFu) {
+                const uint32_t v = l2s[base + (uint32_t)((buf << kLutBits) >> (64 - l2k))];
+                L = v >> 16;
+                sym = v & 0xFFFFu;
+            }
+            if (L == 0) L = lc.decode(buf, sym);
             if (L == 0 || L > valid) {
                 // longer than the buffered bits (only codes > 32 bits): exact window
-                L = lc.decode(window_at(words, nw, pos), sym);
+                L = lc.decode(window_at(words, nwl, pos), sym);
                 if (L == 0) {
                     bad = true;
                     break;
@@ -392,14 +539,14 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
             buf <<= tl;
             valid -= tl;
         } else {
-            const uint32_t kk = pos >> 5, s = pos & 31;
-            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << s;
+            const uint32_t kk = pos >> 5, sh = pos & 31;
+            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << sh;
             wr.rd = kk + 2;
-            valid = 64 - s;
+            valid = 64 - sh;
         }
     }
     // tail: one codeword at a time
-    while (!bad && j < nsym) {
+    while (!bad && j < want) {
         if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
         if (valid < 32) {
             buf |= (uint64_t)wr.pop() << (32 - valid);
@@ -411,7 +558,7 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
         if (((e >> 48) & 3u) == 0) {
             L = lc.decode(buf, sym);
             if (L == 0 || L > valid) {
-                L = lc.decode(window_at(words, nw, pos), sym);
+                L = lc.decode(window_at(words, nwl, pos), sym);
                 if (L == 0) {
                     bad = true;
                     break;
@@ -425,14 +572,17 @@ __global__ __launch_bounds__(kBlock) void k_huff_decode(const FieldDesc* __restr
             buf <<= L;
             valid -= L;
         } else {
-            const uint32_t kk = pos >> 5, s = pos & 31;
-            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << s;
+            const uint32_t kk = pos >> 5, sh = pos & 31;
+            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << sh;
             wr.rd = kk + 2;
-            valid = 64 - s;
+            valid = 64 - sh;
         }
     }
     if (!bad) acc.flush(out);
-    if (bad || pos > nbits) atomicMin(&dy->status, ST_ERR_ARCHIVE);
+    // the first half must end exactly at the midpoint, the second within the chunk
+    const uint32_t end = w0 * 32 + pos;
+    if (bad || end > nbits || (split && half == 0 && nsym > hc / 2 && end != mid))
+        atomicMin(&dy->status, ST_ERR_ARCHIVE);
 }
 
 // Huffman decompression prologue: word counts of every chunk into the
@@ -445,7 +595,8 @@ __global__ __launch_bounds__(kBlock) void k_huff_prep(const FieldDesc* __restric
     const FieldDesc& fd = F[f];
     const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x;
     if (fd.dyn->codec != ARC_HUFFMAN || c >= fd.n_hch) return;
-    const uint32_t nbits = ((const EBC_G uint32_t*)(fd.arc + fd.off_bits))[c];
+    const uint32_t ent = ((const EBC_G uint32_t*)(fd.arc + fd.off_bits))[c];
+    const uint32_t nbits = fd.hc <= 1024 ? ent & 0xFFFFu : ent;
     wcnt[fd.hch_base + c] = (nbits + 31) / 32;
 }
 
@@ -510,7 +661,7 @@ hipError_t launch_huff_decode(const FieldDesc* F, int nf, uint32_t units, const 
                               const uint8_t* tabs, size_t tab_stride, hipStream_t s)
 {
     if (!units) return hipSuccess;
-    hipLaunchKernelGGL(k_huff_decode, dim3(units), dim3(kBlock), 0, s, F, nf, woff, tabs, tab_stride);
+    hipLaunchKernelGGL(k_huff_decode, dim3(units), dim3(kDecBlock), 0, s, F, nf, woff, tabs, tab_stride);
     return hipGetLastError();
 }
 

@@ -14,8 +14,7 @@
 
 namespace ebc {
 
-constexpr uint32_t kSegPerWave = 256;
-constexpr uint32_t kSegPerBlock = kSegPerWave * kWavesPerBlock;
+constexpr uint32_t kSegPerBlock = kBlock;  // one segment per thread
 
 uint32_t outlier_write_units(uint32_t n_seg) { return (n_seg + kSegPerBlock - 1) / kSegPerBlock; }
 
@@ -34,50 +33,48 @@ __device__ __forceinline__ void seg_range(const FieldDesc& fd, uint32_t s, uint6
     }
 }
 
+// One thread per row segment (at most 256 elements).  A thread whose
+// segment holds outliers scans its codes for the placeholder 0 and writes
+// the outliers in index order from the segment's scanned offset; all such
+// threads of a wave scan concurrently.
 __global__ __launch_bounds__(kBlock) void k_outlier_write(const FieldDesc* __restrict__ F, int nf,
                                                           const uint32_t* __restrict__ soff)
 {
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::ow_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
+    const auto* dy = kconst(fd.dyn);
     if (dy->status != ST_OK || dy->codec == ARC_CONST || dy->n_out == 0) return;
-    const int l = lane_id();
+    const uint32_t sg = (t - fd.ow_base) * kSegPerBlock + threadIdx.x;
+    if (sg >= fd.n_seg) return;
     const uint32_t* off = soff + fd.seg_base;
-    const uint32_t off0 = off[0];
+    const uint32_t o0 = off[sg], o1 = off[sg + 1];
+    if (o0 == o1) return;
     EBC_G uint32_t* oidx = (EBC_G uint32_t*)(fd.arc + dy->off_oidx);
     EBC_G int32_t* oval = (EBC_G int32_t*)(fd.arc + dy->off_oval);
-    const uint32_t s_lo = (t - fd.ow_base) * kSegPerBlock + (threadIdx.x / kWave) * kSegPerWave;
-    for (uint32_t sb = s_lo; sb < s_lo + kSegPerWave && sb < fd.n_seg; sb += kWave) {
-        const uint32_t s = sb + l;
-        const bool ok = s < fd.n_seg;
-        const uint32_t o0 = ok ? off[s] : 0u, o1 = ok ? off[s + 1] : 0u;
-        uint64_t todo = ballot(ok && o1 != o0);
-        while (todo) {
-            const int j = __ffsll((long long)todo) - 1;
-            todo &= todo - 1;
-            const uint32_t seg = sb + j;
-            const uint32_t base = __shfl(o0, j) - off0;
-            uint64_t a, b;
-            seg_range(fd, seg, a, b);
-            // a segment spans at most 256 elements: 4 per lane
-            uint32_t zm = 0;
-            const uint64_t e0 = a + 4 * (uint64_t)l;
+    uint32_t pos = o0 - off[0];
+    const uint32_t end = o1 - off[0];
+    uint64_t a, b;
+    seg_range(fd, sg, a, b);
+    const EBC_G uint16_t* q = fd.q;
+    uint64_t i = a;
+    // 8 codes at a time where aligned
+    for (; i < b && (i & 7); ++i)
+        if (q[i] == 0 && pos < end) oidx[pos] = (uint32_t)i, oval[pos] = fd.dsc[i], ++pos;
+    for (; i + 8 <= b && pos < end; i += 8) {
+        const uint4 v = *(const EBC_G uint4*)(q + i);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                if (e0 + k < b && fd.q[e0 + k] == 0) zm |= 1u << k;
-            const uint32_t mine = __popc(zm);
-            uint32_t pos = base + wave_incl_scan_u32(mine) - mine;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (zm & (1u << k)) {
-                    oidx[pos] = (uint32_t)(e0 + k);
-                    oval[pos] = fd.dsc[e0 + k];
-                    ++pos;
-                }
+        for (int k = 0; k < 8; ++k) {
+            if (((w[k / 2] >> (16 * (k & 1))) & 0xFFFFu) == 0 && pos < end) {
+                oidx[pos] = (uint32_t)(i + k);
+                oval[pos] = fd.dsc[i + k];
+                ++pos;
             }
         }
     }
+    for (; i < b && pos < end; ++i)
+        if (q[i] == 0) oidx[pos] = (uint32_t)i, oval[pos] = fd.dsc[i], ++pos;
 }
 
 // ------------------------------------------------------------- decoding

@@ -307,22 +307,28 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
             const int nv_x = x0 >= nx ? 0 : (int)min<uint32_t>(4, nx - x0);
             const uint64_t rowmask = 0x0101010101010101ull << y;
             int32_t fprev[4] = {0, 0, 0, 0};
-            float v[4], vn[4];
-            {
-                const bool ok = yy < ny && z0 < nz;
-                load_quad<VEC>(in, ((uint64_t)z0 * ny + yy) * nx + x0, ok ? nv_x : 0, v);
+            // planes in flight kAhead ahead of the one being processed (the
+            // loop is unrolled, so only those planes occupy registers)
+            constexpr int kAhead = 1;
+            float v[8][4];
+#pragma unroll
+            for (int iz = 0; iz < kAhead; ++iz) {
+                const bool ok = yy < ny && z0 + iz < nz;
+                load_quad<VEC>(in, ((uint64_t)(z0 + iz) * ny + yy) * nx + x0, ok ? nv_x : 0, v[iz]);
             }
+#pragma unroll
             for (int iz = 0; iz < 8; ++iz) {
+                if (iz + kAhead < 8) {
+                    const bool ok = yy < ny && z0 + iz + kAhead < nz;
+                    load_quad<VEC>(in, ((uint64_t)(z0 + iz + kAhead) * ny + yy) * nx + x0, ok ? nv_x : 0,
+                                   v[iz + kAhead]);
+                }
                 const uint32_t z = z0 + iz;
                 const bool rowok = yy < ny && z < nz;
                 const int nv = rowok ? nv_x : 0;
                 const uint64_t i0 = ((uint64_t)z * ny + yy) * nx + x0;
-                if (iz < 7) {  // next plane in flight while this one is processed
-                    const bool okn = yy < ny && z + 1 < nz;
-                    load_quad<VEC>(in, i0 + (uint64_t)ny * nx, okn ? nv_x : 0, vn);
-                }
                 int32_t d[4], e[4], dl[4];
-                prequant4(v, qc.inv, d);
+                prequant4(v[iz], qc.inv, d);
                 int left = dpp_shr<8>(d[3]);
                 if ((xq & 1) == 0) left = 0;  // x chunk boundary
                 e[0] = d[0] - left, e[1] = d[1] - d[0], e[2] = d[2] - d[1], e[3] = d[3] - d[2];
@@ -339,8 +345,6 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
                 store_codes<VEC>(qo, i0, nv, code);
                 const uint32_t cnt = row_count(om, rowmask);
                 if (xq == 0 && cnt) atomicAdd(&s_cnt[wyi * 64 + iz * 8 + y], cnt);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[k] = vn[k];
             }
         } else {
             // lane = 16 * xq + y: y-neighbour at lane - 1 (same DPP row),
@@ -350,23 +354,21 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
             const uint64_t rowmask = 0x0001000100010001ull << y;
             const bool yok = yy < ny;
             uint32_t rowcnt = 0;
-            float v[4], vn[4];
-            {
-                const uint32_t x0 = xb * fd.xs + wxi * 64 + 4 * xq;
+            // the four chunks of the wave in flight at once
+            float v[4][4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * c + 4 * xq;
                 const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
-                load_quad<VEC>(in, (uint64_t)yy * nx + x0, nv, v);
+                load_quad<VEC>(in, (uint64_t)yy * nx + x0, nv, v[c]);
             }
+#pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * c + 4 * xq;
                 const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
                 const uint64_t i0 = (uint64_t)yy * nx + x0;
-                if (c < 3) {
-                    const uint32_t x1 = x0 + 16;
-                    const int nv1 = (!yok || x1 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x1);
-                    load_quad<VEC>(in, i0 + 16, nv1, vn);
-                }
                 int32_t d[4], dl[4];
-                prequant4(v, qc.inv, d);
+                prequant4(v[c], qc.inv, d);
                 int left = __shfl_up(d[3], 16);
                 if (xq == 0) left = 0;  // x chunk boundary
                 int32_t e[4] = {d[0] - left, d[1] - d[0], d[2] - d[1], d[3] - d[2]};
@@ -376,8 +378,6 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
                 const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
                 store_codes<VEC>(qo, i0, nv, code);
                 rowcnt += row_count(om, rowmask);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) v[k] = vn[k];
             }
             if (xq == 0 && rowcnt) atomicAdd(&s_cnt[wyi * 16 + y], rowcnt);
         }

@@ -132,15 +132,20 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
             const uint32_t z0 = zb * 8;
             const int nv_x = x0 >= nx ? 0 : (int)min<uint32_t>(4, nx - x0);
             uint32_t zprev[4] = {0, 0, 0, 0};
-            uint32_t c[4], cn[4];
-            load_codes<VEC>(q, ((uint64_t)z0 * ny + yy) * nx + x0, (yy < ny && z0 < nz) ? nv_x : 0, c);
+            // the whole 8-plane column of codes in flight at once
+            uint32_t c[8][4];
+#pragma unroll
+            for (int iz = 0; iz < 8; ++iz) {
+                const bool ok = yy < ny && z0 + iz < nz;
+                load_codes<VEC>(q, ((uint64_t)(z0 + iz) * ny + yy) * nx + x0, ok ? nv_x : 0, c[iz]);
+            }
+#pragma unroll
             for (int iz = 0; iz < 8; ++iz) {
                 const uint32_t z = z0 + iz;
                 const int nv = (yy < ny && z < nz) ? nv_x : 0;
                 const uint64_t i0 = ((uint64_t)z * ny + yy) * nx + x0;
-                if (iz < 7) load_codes<VEC>(q, i0 + (uint64_t)ny * nx, (yy < ny && z + 1 < nz) ? nv_x : 0, cn);
                 uint32_t s[4];
-                fuse4(c, nv, r, dsc, i0, s, zeros);
+                fuse4(c[iz], nv, r, dsc, i0, s, zeros);
                 // x pass: within the quad, then the quad to the left in the chunk
                 s[1] += s[0], s[2] += s[1], s[3] += s[2];
                 uint32_t left = dpp_shr_u<8>(s[3]);
@@ -163,31 +168,27 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
                 float v[4];
                 dequant4(s, ebx2, v);
                 store_quad<VEC>(out, i0, nv, v);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = cn[k];
             }
         } else {
             // lane = 16 * xq + y, four 16x16 chunks along x per wave
             const uint32_t y = l & 15, xq = l >> 4;
             const uint32_t yy = yb * 16 * wy + wyi * 16 + y;
             const bool yok = yy < ny;
-            uint32_t c[4], cn[4];
-            {
-                const uint32_t x0 = xb * fd.xs + wxi * 64 + 4 * xq;
+            // the four chunks of the wave in flight at once
+            uint32_t c[4][4];
+#pragma unroll
+            for (int ch = 0; ch < 4; ++ch) {
+                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * ch + 4 * xq;
                 const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
-                load_codes<VEC>(q, (uint64_t)yy * nx + x0, nv, c);
+                load_codes<VEC>(q, (uint64_t)yy * nx + x0, nv, c[ch]);
             }
+#pragma unroll
             for (int ch = 0; ch < 4; ++ch) {
                 const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * ch + 4 * xq;
                 const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
                 const uint64_t i0 = (uint64_t)yy * nx + x0;
-                if (ch < 3) {
-                    const uint32_t x1 = x0 + 16;
-                    const int nv1 = (!yok || x1 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x1);
-                    load_codes<VEC>(q, i0 + 16, nv1, cn);
-                }
                 uint32_t s[4];
-                fuse4(c, nv, r, dsc, i0, s, zeros);
+                fuse4(c[ch], nv, r, dsc, i0, s, zeros);
                 // x pass: within the quad, then over the 4 quads of the chunk row
                 s[1] += s[0], s[2] += s[1], s[3] += s[2];
                 const uint32_t tot = s[3];
@@ -209,8 +210,6 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
                 float v[4];
                 dequant4(s, ebx2, v);
                 store_quad<VEC>(out, i0, nv, v);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) c[k] = cn[k];
             }
         }
     }

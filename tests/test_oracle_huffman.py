@@ -189,14 +189,38 @@ def test_huffman_encode_decode_roundtrip(h):
         q = rng.choice(h.size, size=n, p=p).astype(np.uint16)
         ln = O.huffman_lengths(O.histogram(q, h.size))
         code = O.canonical_codes(ln)
-        bits, words = O.huffman_encode(q, ln, code, hc)
-        # chunk bit counts are the code-length sums; words per chunk are ceil(bits/32)
-        for c in range(bits.size):
-            assert bits[c] == int(ln[q[c * hc:(c + 1) * hc]].astype(np.int64).sum())
+        ent, words = O.huffman_encode(q, ln, code, hc)
+        # chunk entries: the code-length sum in the low half and the bit offset
+        # of the chunk's symbol hc/2 (the sum itself for a short chunk) in the
+        # high half; words per chunk are ceil(bits/32)
+        bits = ent & 0xFFFF
+        for c in range(ent.size):
+            chunk = ln[q[c * hc:(c + 1) * hc]].astype(np.int64)
+            assert bits[c] == int(chunk.sum())
+            mid = int(chunk[:hc // 2].sum()) if chunk.size > hc // 2 else int(chunk.sum())
+            assert ent[c] >> 16 == mid
         assert words.size == int(((bits.astype(np.int64) + 31) // 32).sum())
         # payload never below one bit per symbol (CR <= 32 for fp32, Sec. II-B.1)
         assert int(bits.astype(np.int64).sum()) >= n
-        np.testing.assert_array_equal(O.huffman_decode(bits, words, n, ln, hc), q)
+        np.testing.assert_array_equal(O.huffman_decode(ent, words, n, ln, hc), q)
+        # a wrong midpoint is a corrupt archive
+        if ent.size:
+            bad = ent.copy()
+            bad[0] ^= 1 << 16
+            with pytest.raises(O.OracleError):
+                O.huffman_decode(bad, words, n, ln, hc)
+
+
+def test_huffman_chunk_entry_without_midpoint_above_1024():
+    """For chunks longer than 1024 symbols the entry is the plain bit count."""
+    rng = np.random.default_rng(32)
+    q = rng.integers(0, 5, size=5000).astype(np.uint16)
+    ln = O.huffman_lengths(O.histogram(q, 5))
+    code = O.canonical_codes(ln)
+    ent, words = O.huffman_encode(q, ln, code, 2048)
+    for c in range(ent.size):
+        assert ent[c] == int(ln[q[c * 2048:(c + 1) * 2048]].astype(np.int64).sum())
+    np.testing.assert_array_equal(O.huffman_decode(ent, words, q.size, ln, 2048), q)
 
 
 def test_huffman_bitstream_layout_msb_first():
@@ -207,7 +231,7 @@ def test_huffman_bitstream_layout_msb_first():
     assert list(ln) == [1, 2, 2] and list(code) == [0, 2, 3]
     q = np.array([0, 1, 2, 0], np.uint16)
     bits, words = O.huffman_encode(q, ln, code, 64)
-    assert list(bits) == [6]
+    assert list(bits) == [6 | (6 << 16)]  # 6 bits; no symbol 32, so the midpoint is the end
     assert list(words) == [0b010110 << 26]
 
 

@@ -174,7 +174,7 @@ Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc)
     g.n = g.nx * g.ny * g.nz;
     const Tune t = lookup_tune(rank, dims);
     g.wx = rank > 1 && t.wx ? t.wx : choose_wx(rank, g.nx);
-    g.grid = t.grid ? t.grid : kConstructBlocks;
+    g.grid = t.grid;  // 0: as many workgroups as the device holds at once
     if (rank == 1) {
         g.xs = 256;
         g.nxb = 1, g.nyb = 1, g.nzb = 1;
@@ -241,7 +241,28 @@ struct Batch {
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 // Group fields by (rank, vec) and assign every work-unit base.
-void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec)
+// Default persistent construction grid for a (rank, layout) variant: the
+// workgroups the device holds at once, cached per device and bin count.
+uint32_t resident_grid(int rank, bool vec, uint32_t n_bins)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<uint64_t, uint32_t>> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const uint64_t key = ((uint64_t)dev << 32) | ((uint64_t)n_bins << 3) | (uint64_t)(rank * 2 + (vec ? 1 : 0));
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const auto& kv : cache)
+            if (kv.first == key) return kv.second;
+    }
+    uint32_t g = construct_resident_blocks(rank, vec, n_bins);
+    if (g == 0) g = kConstructBlocks;
+    std::lock_guard<std::mutex> lk(mu);
+    cache.push_back({key, g});
+    return g;
+}
+
+void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec, uint32_t n_bins)
 {
     const int nf = B.nf;
     std::vector<int> idx(nf);
@@ -275,6 +296,7 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
     for (auto& G : B.groups) {
         uint32_t grid = 0;
         for (int k = G.first; k < G.first + G.count; ++k) grid = std::max(grid, geo[B.order[k]].grid);
+        if (grid == 0) grid = n_bins ? resident_grid(G.rank, G.vec, n_bins) : kConstructBlocks;
         G.blocks = std::min(G.wg_tiles, grid);
         for (int k = G.first; k < G.first + G.count; ++k)
             B.fd[k].hrows = std::min(B.fd[k].wg_tiles, G.blocks);
@@ -313,7 +335,7 @@ void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P
         geo[i] = make_geo(fin[i].rank, fin[i].dims, P.hc);
         vec[i] = aligned16(fin[i].in) && (fin[i].rank == 1 || geo[i].nx % 4 == 0);
     }
-    assign_bases(B, geo, vec);
+    assign_bases(B, geo, vec, P.n_bins);
     Bump bp{ws};
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
@@ -562,7 +584,7 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         geo[i] = make_geo(H.rank, H.dims, H.hc);
         vec[i] = aligned16(din[i].out) && (H.rank == 1 || geo[i].nx % 4 == 0);
     }
-    assign_bases(B, geo, vec);
+    assign_bases(B, geo, vec, 0);  // no construction grid needed
     Bump bp{ws};
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
@@ -601,6 +623,9 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
             d.wg_tiles = wt;
             G.wg_tiles += wt;
         }
+        uint32_t grid = reconstruct_resident_blocks(G.rank, G.vec);
+        if (grid == 0) grid = kConstructBlocks;
+        G.blocks = std::min(G.wg_tiles, grid);
     }
     B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
     B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
@@ -631,7 +656,7 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         const bool cst = H.codec == EBC_ARC_CONST;
         d.q = bp.take<uint16_t>(cst ? 0 : 2 * g.n);
         d.dsc = bp.take<int32_t>(cst ? 0 : 4 * g.n);
-        d.zpart = bp.take<uint32_t>(4ull * std::max(d.wg_tiles, 1u));
+        d.sink = bp.take<float>(256);
     }
     B.ws_bytes = bp.off;
 }
@@ -659,7 +684,7 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     HIP_TRY(launch_outlier_scatter(B.d_fd, nf, B.tot_sc, s));
     T.mark("reconstruct");
     for (const auto& G : B.groups)
-        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, s));
+        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
     T.mark("check");
     HIP_TRY(launch_recon_check(B.d_fd, nf, s));
     HIP_TRY(launch_fill_const(B.d_fd, nf, B.tot_range, s));
@@ -1188,7 +1213,7 @@ int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int
     HIP_TRY(launch_dinit(B.d_fd, 1, s));
     HIP_TRY(launch_outlier_scatter(B.d_fd, 1, B.tot_sc, s));
     for (const auto& G : B.groups)
-        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, s));
+        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
     HIP_TRY(launch_recon_check(B.d_fd, 1, s));
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);

@@ -23,6 +23,7 @@ hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s);
 // quantisation
 hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s);
+uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins);
 hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
                             uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s);
 hipError_t launch_hist_reduce(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s);
@@ -58,8 +59,9 @@ hipError_t launch_outlier_write(const FieldDesc* F, int nf, uint32_t units, cons
 hipError_t launch_outlier_scatter(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 
 // reconstruction
+uint32_t reconstruct_resident_blocks(int rank, bool vec);
 hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
-                              hipStream_t s);
+                              uint32_t blocks, hipStream_t s);
 hipError_t launch_recon_check(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_dinit(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_fill_const(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);

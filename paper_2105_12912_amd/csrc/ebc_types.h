@@ -90,6 +90,7 @@ struct FieldDesc {
     // buffers (device)
     const EBC_G float* in;   // compress input
     EBC_G float* outf;       // decompress output
+    EBC_G float* sink;       // decompress: 256 bytes that absorb stores of absent elements
     EBC_G uint8_t* arc;      // archive (compress output / decompress input)
     uint64_t arc_cap;        // compress: capacity; decompress: archive size
     EBC_G uint16_t* q;       // quant-codes, n
@@ -102,7 +103,6 @@ struct FieldDesc {
     EBC_G uint8_t* len;      // n_bins code lengths
     EBC_G uint32_t* hbits;   // per Huffman chunk bit counts
     EBC_G uint32_t* rstart;  // RLE run starts (compress scratch)
-    EBC_G uint32_t* zpart;   // per WG-tile zero counts (decompress validation)
     EBC_G FieldDyn* dyn;
     // this field's work units in each batch-wide index space
     uint32_t range_units, range_base;  // value range / fill: kRangeUnit elements per WG

@@ -488,6 +488,28 @@ hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s)
     return hipGetLastError();
 }
 
+// Workgroups of one construction variant that the device holds at once (the
+// default persistent grid); 0 if the query fails.
+uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const size_t sh = (size_t)n_bins * sizeof(uint32_t);
+    hipError_t e;
+    if (rank == 1)
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<1, true>, kBlock, sh)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<1, false>, kBlock, sh);
+    else if (rank == 2)
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<2, true>, kBlock, sh)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<2, false>, kBlock, sh);
+    else
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<3, true>, kBlock, sh)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<3, false>, kBlock, sh);
+    if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
+    return (uint32_t)(per * cus);
+}
+
 hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
                             uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s)
 {

@@ -19,29 +19,33 @@
 
 namespace ebc {
 
+// Four codes kept packed (two per 32-bit word) so that a whole tile's loads
+// fit in few registers; codes of absent elements read as 1 (never the
+// outlier placeholder).
 template <bool VEC>
-__device__ __forceinline__ void load_codes(const EBC_G uint16_t* __restrict__ q, uint64_t i, int nvalid,
-                                           uint32_t c[4])
+__device__ __forceinline__ u32x2 load_packed(const EBC_G uint16_t* __restrict__ q, uint64_t i, int nvalid)
 {
-    if (VEC) {
-        if (nvalid == 4) {
-            const u32x2 t = ld_nt_u2(q + i);
-            c[0] = t.x & 0xFFFF, c[1] = t.x >> 16, c[2] = t.y & 0xFFFF, c[3] = t.y >> 16;
-        } else {
-            c[0] = c[1] = c[2] = c[3] = 1;  // never used; non-zero so no outlier lookup
-        }
-    } else {
+    if (VEC && nvalid == 4) return ld_nt_u2(q + i);
+    uint32_t c[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = k < nvalid ? q[i + k] : 1u;
-    }
+    for (int k = 0; k < 4; ++k) c[k] = k < nvalid ? q[i + k] : 1u;
+    u32x2 t;
+    t.x = c[0] | (c[1] << 16);
+    t.y = c[2] | (c[3] << 16);
+    return t;
+}
+
+__device__ __forceinline__ void unpack4(u32x2 t, uint32_t c[4])
+{
+    c[0] = t.x & 0xFFFF, c[1] = t.x >> 16, c[2] = t.y & 0xFFFF, c[3] = t.y >> 16;
 }
 
 template <bool VEC>
 __device__ __forceinline__ void store_quad(EBC_G float* __restrict__ o, uint64_t i, int nvalid,
                                            const float v[4])
 {
-    if (VEC) {
-        if (nvalid == 4) st_nt_f4(o + i, f32x4{v[0], v[1], v[2], v[3]});
+    if (VEC && nvalid == 4) {
+        st_nt_f4(o + i, f32x4{v[0], v[1], v[2], v[3]});
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
@@ -58,6 +62,10 @@ __device__ __forceinline__ void fuse4(const uint32_t c[4], int nvalid, int32_t r
     for (int k = 0; k < 4; ++k) {
         if (c[k] == 0 && k < nvalid) {
             qp[k] = (uint32_t)dsc[i + k];
+            // consume the loaded value inside the (rare) branch, so that the
+            // wait for it stays here and the common path never waits on the
+            // loads and stores in flight
+            asm volatile("" ::"v"(qp[k]));
             ++zeros;
         } else {
             qp[k] = c[k] - (uint32_t)r;
@@ -71,173 +79,225 @@ __device__ __forceinline__ void dequant4(const uint32_t s[4], double ebx2, float
     for (int k = 0; k < 4; ++k) v[k] = (float)((double)(int32_t)s[k] * ebx2);
 }
 
-template <int RANK, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restrict__ F, int nf)
+// This lane's quads of one workgroup tile: four 256-long chunks' quads (1D),
+// four chunks along x (2D) or the eight z-planes of the chunk column (3D).
+template <int RANK>
+struct RTile {
+    static constexpr int NQ = RANK == 3 ? 8 : 4;
+    u32x2 raw[NQ];
+};
+
+// lane geometry of a tile: first element of quad k and its valid count
+template <int RANK>
+__device__ __forceinline__ void rquad(const FieldDesc& fd, uint32_t tl, int k, uint64_t& i0, int& nv)
 {
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const int l = lane_id();
     const uint32_t w = threadIdx.x / kWave;
-    const uint32_t tl = t - fd.wg_base;
-    const int32_t r = (int32_t)(fd.n_bins / 2);
-    const double ebx2 = dy->ebx2;
-    const EBC_G uint16_t* __restrict__ q = fd.q;
-    const EBC_G int32_t* __restrict__ dsc = fd.dsc;
-    EBC_G float* __restrict__ out = fd.outf;
-    uint32_t zeros = 0;
-
     if (RANK == 1) {
         const uint32_t wt = tl * kWavesPerBlock + w;
-        if (wt < fd.n_wave_tiles) {
-            const uint64_t n = fd.n;
-            uint32_t c[4][4];
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                const uint64_t i0 = (uint64_t)wt * 1024 + ch * 256 + 4 * l;
-                const int nv = i0 >= n ? 0 : (int)min<uint64_t>(4, n - i0);
-                if (VEC && nv == 4) load_codes<true>(q, i0, 4, c[ch]);
-                else load_codes<false>(q, i0, nv, c[ch]);
-            }
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                const uint64_t i0 = (uint64_t)wt * 1024 + ch * 256 + 4 * l;
-                const int nv = i0 >= n ? 0 : (int)min<uint64_t>(4, n - i0);
-                uint32_t s[4];
-                fuse4(c[ch], nv, r, dsc, i0, s, zeros);
-                s[1] += s[0], s[2] += s[1], s[3] += s[2];
-                // exclusive prefix of the lane totals over the 256-long chunk
-                const uint32_t excl = wave_incl_scan_u32(s[3]) - s[3];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) s[k] += excl;
-                float v[4];
-                dequant4(s, ebx2, v);
-                if (VEC && nv == 4) store_quad<true>(out, i0, 4, v);
-                else store_quad<false>(out, i0, nv, v);
-            }
-        }
+        i0 = (uint64_t)wt * 1024 + k * 256 + 4 * l;
+        nv = (wt >= fd.n_wave_tiles || i0 >= fd.n) ? 0 : (int)min<uint64_t>(4, fd.n - i0);
+        if (nv == 0) i0 = 0;
+        return;
+    }
+    const uint32_t wx = fd.wx, wy = kWavesPerBlock / wx;
+    const uint32_t wxi = w % wx, wyi = w / wx;
+    const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+    const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+    const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+    uint32_t x0, yy, z;
+    if (RANK == 3) {
+        const uint32_t y = l & 7, xq = l >> 3;
+        x0 = xb * fd.xs + wxi * 32 + 4 * xq;
+        yy = yb * 8 * wy + wyi * 8 + y;
+        z = zb * 8 + k;
     } else {
-        const uint32_t wx = fd.wx, wy = kWavesPerBlock / wx;
-        const uint32_t wxi = w % wx, wyi = w / wx;
-        const uint32_t nxb = fd.nxb, nyb = fd.nyb;
-        const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
-        const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
-        if (RANK == 3) {
-            // lane = 8 * xq + y, one z-plane of an 8x8x8 chunk pair per step
+        const uint32_t y = l & 15, xq = l >> 4;
+        x0 = xb * fd.xs + wxi * 64 + 16 * k + 4 * xq;
+        yy = yb * 16 * wy + wyi * 16 + y;
+        z = 0;
+    }
+    const bool ok = x0 < nx && yy < ny && z < nz;
+    nv = ok ? (int)min<uint32_t>(4, nx - x0) : 0;
+    i0 = ok ? ((uint64_t)z * ny + yy) * nx + x0 : 0;
+}
+
+// With 16-byte rows (VEC) every quad is loaded with one unconditional vector
+// load (an absent quad reads the start of the code array; the tail quad of a
+// 1D field may read up to 6 bytes past the codes, into the outlier scratch
+// that follows them), so the number of memory operations per tile is fixed
+// and the compiler never has to wait for stores before a load's use.
+template <int RANK, bool VEC>
+__device__ __forceinline__ void rtile_load(const FieldDesc& fd, uint32_t tl, RTile<RANK>& T)
+{
+#pragma unroll
+    for (int k = 0; k < RTile<RANK>::NQ; ++k) {
+        uint64_t i0;
+        int nv;
+        rquad<RANK>(fd, tl, k, i0, nv);
+        if (VEC) T.raw[k] = ld_nt_u2(fd.q + (nv > 0 ? i0 : 0));
+        else T.raw[k] = load_packed<false>(fd.q, i0, nv);
+    }
+}
+
+template <int RANK, bool VEC>
+__device__ __forceinline__ void rtile_process(const FieldDesc& fd, uint32_t tl, const RTile<RANK>& T,
+                                              double ebx2, uint32_t& zeros)
+{
+    const int l = lane_id();
+    const int32_t r = (int32_t)(fd.n_bins / 2);
+    const EBC_G int32_t* __restrict__ dsc = fd.dsc;
+    EBC_G float* __restrict__ out = fd.outf;
+    uint32_t zprev[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < RTile<RANK>::NQ; ++k) {
+        uint64_t i0;
+        int nv;
+        rquad<RANK>(fd, tl, k, i0, nv);
+        uint32_t c[4], s[4];
+        unpack4(T.raw[k], c);
+        if (VEC) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (j >= nv) c[j] = 1u;  // absent: never the outlier placeholder
+        }
+        fuse4(c, nv, r, dsc, i0, s, zeros);
+        s[1] += s[0], s[2] += s[1], s[3] += s[2];  // x pass within the quad
+        if (RANK == 1) {
+            // exclusive prefix of the lane totals over the 256-long chunk
+            const uint32_t excl = wave_incl_scan_u32(s[3]) - s[3];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) s[j] += excl;
+        } else if (RANK == 3) {
             const uint32_t y = l & 7, xq = l >> 3;
-            const uint32_t x0 = xb * fd.xs + wxi * 32 + 4 * xq;
-            const uint32_t yy = yb * 8 * wy + wyi * 8 + y;
-            const uint32_t z0 = zb * 8;
-            const int nv_x = x0 >= nx ? 0 : (int)min<uint32_t>(4, nx - x0);
-            uint32_t zprev[4] = {0, 0, 0, 0};
-            // the whole 8-plane column of codes in flight at once
-            uint32_t c[8][4];
+            uint32_t left = dpp_shr_u<8>(s[3]);  // the quad to the left in the chunk
+            if ((xq & 1) == 0) left = 0;
 #pragma unroll
-            for (int iz = 0; iz < 8; ++iz) {
-                const bool ok = yy < ny && z0 + iz < nz;
-                load_codes<VEC>(q, ((uint64_t)(z0 + iz) * ny + yy) * nx + x0, ok ? nv_x : 0, c[iz]);
-            }
-#pragma unroll
-            for (int iz = 0; iz < 8; ++iz) {
-                const uint32_t z = z0 + iz;
-                const int nv = (yy < ny && z < nz) ? nv_x : 0;
-                const uint64_t i0 = ((uint64_t)z * ny + yy) * nx + x0;
-                uint32_t s[4];
-                fuse4(c[iz], nv, r, dsc, i0, s, zeros);
-                // x pass: within the quad, then the quad to the left in the chunk
-                s[1] += s[0], s[2] += s[1], s[3] += s[2];
-                uint32_t left = dpp_shr_u<8>(s[3]);
-                if ((xq & 1) == 0) left = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) s[k] += left;
+            for (int j = 0; j < 4; ++j) {
+                s[j] += left;
                 // y pass: inclusive scan over the 8 lanes of the chunk column
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    uint32_t a = dpp_shr_u<1>(s[k]);
-                    s[k] += y >= 1 ? a : 0u;
-                    a = dpp_shr_u<2>(s[k]);
-                    s[k] += y >= 2 ? a : 0u;
-                    a = dpp_shr_u<4>(s[k]);
-                    s[k] += y >= 4 ? a : 0u;
-                    // z pass: running sum over the planes of the chunk
-                    s[k] += zprev[k];
-                    zprev[k] = s[k];
-                }
-                float v[4];
-                dequant4(s, ebx2, v);
-                store_quad<VEC>(out, i0, nv, v);
+                uint32_t a = dpp_shr_u<1>(s[j]);
+                s[j] += y >= 1 ? a : 0u;
+                a = dpp_shr_u<2>(s[j]);
+                s[j] += y >= 2 ? a : 0u;
+                a = dpp_shr_u<4>(s[j]);
+                s[j] += y >= 4 ? a : 0u;
+                // z pass: running sum over the planes of the chunk
+                s[j] += zprev[j];
+                zprev[j] = s[j];
             }
         } else {
-            // lane = 16 * xq + y, four 16x16 chunks along x per wave
-            const uint32_t y = l & 15, xq = l >> 4;
-            const uint32_t yy = yb * 16 * wy + wyi * 16 + y;
-            const bool yok = yy < ny;
-            // the four chunks of the wave in flight at once
-            uint32_t c[4][4];
+            const uint32_t xq = l >> 4;
+            // x pass over the 4 quads of the chunk row
+            const uint32_t tot = s[3];
+            uint32_t inc = tot;
+            uint32_t a = (uint32_t)__shfl_up((int)inc, 16);
+            inc += xq >= 1 ? a : 0u;
+            a = (uint32_t)__shfl_up((int)inc, 32);
+            inc += xq >= 2 ? a : 0u;
+            const uint32_t left = inc - tot;
+            // y pass: the 16 rows of a chunk are the 16 lanes of a DPP row
 #pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * ch + 4 * xq;
-                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
-                load_codes<VEC>(q, (uint64_t)yy * nx + x0, nv, c[ch]);
-            }
-#pragma unroll
-            for (int ch = 0; ch < 4; ++ch) {
-                const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * ch + 4 * xq;
-                const int nv = (!yok || x0 >= nx) ? 0 : (int)min<uint32_t>(4, nx - x0);
-                const uint64_t i0 = (uint64_t)yy * nx + x0;
-                uint32_t s[4];
-                fuse4(c[ch], nv, r, dsc, i0, s, zeros);
-                // x pass: within the quad, then over the 4 quads of the chunk row
-                s[1] += s[0], s[2] += s[1], s[3] += s[2];
-                const uint32_t tot = s[3];
-                uint32_t inc = tot;
-                uint32_t a = (uint32_t)__shfl_up((int)inc, 16);
-                inc += xq >= 1 ? a : 0u;
-                a = (uint32_t)__shfl_up((int)inc, 32);
-                inc += xq >= 2 ? a : 0u;
-                const uint32_t left = inc - tot;
-                // y pass: the 16 rows of a chunk are the 16 lanes of a DPP row
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    s[k] += left;
-                    s[k] += dpp_shr_u<1>(s[k]);
-                    s[k] += dpp_shr_u<2>(s[k]);
-                    s[k] += dpp_shr_u<4>(s[k]);
-                    s[k] += dpp_shr_u<8>(s[k]);
-                }
-                float v[4];
-                dequant4(s, ebx2, v);
-                store_quad<VEC>(out, i0, nv, v);
+            for (int j = 0; j < 4; ++j) {
+                s[j] += left;
+                s[j] += dpp_shr_u<1>(s[j]);
+                s[j] += dpp_shr_u<2>(s[j]);
+                s[j] += dpp_shr_u<4>(s[j]);
+                s[j] += dpp_shr_u<8>(s[j]);
             }
         }
+        float v[4];
+        dequant4(s, ebx2, v);
+        if (VEC) {
+            // one unconditional vector store (absent quads go to the sink);
+            // a partial quad (1D tail only) is then written element-wise
+            st_nt_f4(nv == 4 ? out + i0 : fd.sink, f32x4{v[0], v[1], v[2], v[3]});
+            if (nv > 0 && nv < 4) {
+                for (int j = 0; j < nv; ++j) out[i0 + j] = v[j];
+            }
+        } else {
+            store_quad<false>(out, i0, nv, v);
+        }
     }
-    // zero codes seen by this workgroup (checked against the outlier count)
+}
+
+// Zero codes seen by this workgroup for field fd, added to the field's count
+// (checked against the outlier count by k_recon_check).
+__device__ __forceinline__ void flush_zeros(const FieldDesc& fd, uint32_t& zeros, uint32_t* s_z)
+{
     const uint32_t zs = wave_sum_u32(zeros);
-    __shared__ uint32_t s_z[kWavesPerBlock];
-    if (l == 0) s_z[w] = zs;
+    zeros = 0;
     __syncthreads();
-    if (threadIdx.x == 0) fd.zpart[tl] = s_z[0] + s_z[1] + s_z[2] + s_z[3];
+    if (lane_id() == 0) s_z[threadIdx.x / kWave] = zs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t z = s_z[0] + s_z[1] + s_z[2] + s_z[3];
+        if (z) atomicAdd((unsigned long long*)&fd.dyn->zero_count, (unsigned long long)z);
+    }
+}
+
+// Persistent over the workgroup tiles of one (rank, layout) group, with the
+// next tile's codes in flight while the current tile is reconstructed (two
+// static buffers; the next stage's loads are always issued, past the end they
+// re-read the current tile).
+template <int RANK, bool VEC>
+__global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restrict__ F, int nf,
+                                                        uint32_t n_tiles)
+{
+    __shared__ uint32_t s_z[kWavesPerBlock];
+    uint32_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    RTile<RANK> A, B;
+    int fa = find_field<&FieldDesc::wg_base>(F, nf, t), fb;
+    rtile_load<RANK, VEC>(F[fa], t - F[fa].wg_base, A);
+    int cur = -1;
+    uint32_t zeros = 0;
+    for (;;) {
+        uint32_t tn = t + gridDim.x;
+        const uint32_t tb = tn < n_tiles ? tn : t;
+        fb = find_field<&FieldDesc::wg_base>(F, nf, tb);
+        rtile_load<RANK, VEC>(F[fb], tb - F[fb].wg_base, B);
+        {
+            const FieldDesc& fd = F[fa];
+            const auto* dy = kconst(fd.dyn);
+            if (fa != cur) {
+                if (cur >= 0) flush_zeros(F[cur], zeros, s_z);
+                cur = fa;
+            }
+            if (dy->status == ST_OK && dy->codec != ARC_CONST)
+                rtile_process<RANK, VEC>(fd, t - fd.wg_base, A, dy->ebx2, zeros);
+        }
+        t = tn;
+        if (t >= n_tiles) break;
+        tn = t + gridDim.x;
+        const uint32_t ta = tn < n_tiles ? tn : t;
+        fa = find_field<&FieldDesc::wg_base>(F, nf, ta);
+        rtile_load<RANK, VEC>(F[fa], ta - F[fa].wg_base, A);
+        {
+            const FieldDesc& fd = F[fb];
+            const auto* dy = kconst(fd.dyn);
+            if (fb != cur) {
+                if (cur >= 0) flush_zeros(F[cur], zeros, s_z);
+                cur = fb;
+            }
+            if (dy->status == ST_OK && dy->codec != ARC_CONST)
+                rtile_process<RANK, VEC>(fd, t - fd.wg_base, B, dy->ebx2, zeros);
+        }
+        t = tn;
+        if (t >= n_tiles) break;
+    }
+    if (cur >= 0) flush_zeros(F[cur], zeros, s_z);
 }
 
 // decompression epilogue: the code-0 count must equal the outlier count
-__global__ __launch_bounds__(kBlock) void k_recon_check(const FieldDesc* __restrict__ F)
+__global__ void k_recon_check(const FieldDesc* __restrict__ F, int nf)
 {
-    const FieldDesc& fd = F[blockIdx.x];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    const FieldDesc& fd = F[f];
     EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || fd.codec_hdr == ARC_CONST) return;
-    uint64_t z = 0;
-    for (uint32_t i = threadIdx.x; i < fd.wg_tiles; i += kBlock) z += fd.zpart[i];
-    z = wave_sum_u64(z);
-    __shared__ uint64_t s_z[kWavesPerBlock];
-    if (lane_id() == 0) s_z[threadIdx.x / kWave] = z;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        z = s_z[0] + s_z[1] + s_z[2] + s_z[3];
-        dy->zero_count = z;
-        if (z != fd.n_out_hdr) dy->status = ST_ERR_ARCHIVE;
-    }
+    if (dy->zero_count != fd.n_out_hdr) dy->status = ST_ERR_ARCHIVE;
 }
 
 // decompression prologue: per-field device scalars from the header values
@@ -266,27 +326,47 @@ __global__ __launch_bounds__(kBlock) void k_fill_const(const FieldDesc* __restri
     for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) fd.outf[i] = fd.cval;
 }
 
+// Workgroups of one reconstruction variant the device holds at once.
+uint32_t reconstruct_resident_blocks(int rank, bool vec)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e;
+    if (rank == 1)
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<1, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<1, false>, kBlock, 0);
+    else if (rank == 2)
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, false>, kBlock, 0);
+    else
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<3, true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<3, false>, kBlock, 0);
+    if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
+    return (uint32_t)(per * cus);
+}
+
 hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
-                              hipStream_t s)
+                              uint32_t blocks, hipStream_t s)
 {
     if (wg_tiles == 0) return hipSuccess;
-    const dim3 g(wg_tiles), b(kBlock);
+    const dim3 g(blocks), b(kBlock);
     if (rank == 1) {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<1, true>), g, b, 0, s, F, nf);
-        else hipLaunchKernelGGL((k_reconstruct<1, false>), g, b, 0, s, F, nf);
+        if (vec) hipLaunchKernelGGL((k_reconstruct<1, true>), g, b, 0, s, F, nf, wg_tiles);
+        else hipLaunchKernelGGL((k_reconstruct<1, false>), g, b, 0, s, F, nf, wg_tiles);
     } else if (rank == 2) {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<2, true>), g, b, 0, s, F, nf);
-        else hipLaunchKernelGGL((k_reconstruct<2, false>), g, b, 0, s, F, nf);
+        if (vec) hipLaunchKernelGGL((k_reconstruct<2, true>), g, b, 0, s, F, nf, wg_tiles);
+        else hipLaunchKernelGGL((k_reconstruct<2, false>), g, b, 0, s, F, nf, wg_tiles);
     } else {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<3, true>), g, b, 0, s, F, nf);
-        else hipLaunchKernelGGL((k_reconstruct<3, false>), g, b, 0, s, F, nf);
+        if (vec) hipLaunchKernelGGL((k_reconstruct<3, true>), g, b, 0, s, F, nf, wg_tiles);
+        else hipLaunchKernelGGL((k_reconstruct<3, false>), g, b, 0, s, F, nf, wg_tiles);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_recon_check(const FieldDesc* F, int nf, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_recon_check, dim3(nf), dim3(kBlock), 0, s, F);
+    hipLaunchKernelGGL(k_recon_check, dim3((nf + 63) / 64), dim3(64), 0, s, F, nf);
     return hipGetLastError();
 }
 

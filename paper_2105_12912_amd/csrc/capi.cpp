@@ -315,6 +315,12 @@ void fill_geometry(FieldDesc& d, const Geo& g, bool vec)
     d.vec = vec ? 1u : 0u;
 }
 
+// 3D reconstruction workgroup tiles: 256 x 32 x 8 (a wave per 8-row layer)
+void recon3_tiles(const Geo& g, uint32_t t[3])
+{
+    t[0] = cdiv(g.nx, 256), t[1] = cdiv(g.ny, 32), t[2] = cdiv(g.nz, 8);
+}
+
 // Compression plan: geometry, bases and workspace carving (base == nullptr
 // only sizes the workspace).
 struct CompressIn {
@@ -618,14 +624,17 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         for (int k = G.first; k < G.first + G.count; ++k) {
             FieldDesc& d = B.fd[k];
             const Geo& g = geo[B.order[k]];
-            const uint32_t wt = d.codec_hdr == EBC_ARC_CONST ? 0 : g.wg_tiles;
+            uint32_t wt = d.codec_hdr == EBC_ARC_CONST ? 0 : g.wg_tiles;
+            if (G.rank == 3 && wt) {
+                uint32_t t3[3];
+                recon3_tiles(g, t3);
+                wt = t3[0] * t3[1] * t3[2];
+            }
             d.wg_base = G.wg_tiles;
             d.wg_tiles = wt;
             G.wg_tiles += wt;
         }
-        uint32_t grid = reconstruct_resident_blocks(G.rank, G.vec);
-        if (grid == 0) grid = kConstructBlocks;
-        G.blocks = std::min(G.wg_tiles, grid);
+        G.blocks = G.wg_tiles;  // one workgroup per tile
     }
     B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
     B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
@@ -638,6 +647,12 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         const Geo& g = geo[B.order[k]];
         FieldDesc& d = B.fd[k];
         fill_geometry(d, g, vec[B.order[k]]);
+        if (g.rank == 3) {
+            // the 3D reconstruction kernel tiles differently from construction
+            uint32_t t3[3];
+            recon3_tiles(g, t3);
+            d.nxb = t3[0], d.nyb = t3[1], d.nzb = t3[2];
+        }
         d.n_bins = H.n_bins;
         d.hc = H.hc;
         d.eb_mode = H.eb_mode;

@@ -236,10 +236,10 @@ __device__ __forceinline__ void flush_zeros(const FieldDesc& fd, uint32_t& zeros
     }
 }
 
-// Persistent over the workgroup tiles of one (rank, layout) group, with the
+// Grid-stride over the workgroup tiles of one (rank, layout) group, with the
 // next tile's codes in flight while the current tile is reconstructed (two
-// static buffers; the next stage's loads are always issued, past the end they
-// re-read the current tile).
+// static buffers).  Launched with one workgroup per tile, which measured
+// faster than a resident-size grid; the stride loop serves tuned grids.
 template <int RANK, bool VEC>
 __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restrict__ F, int nf,
                                                         uint32_t n_tiles)
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
         uint32_t tn = t + gridDim.x;
         const uint32_t tb = tn < n_tiles ? tn : t;
         fb = find_field<&FieldDesc::wg_base>(F, nf, tb);
-        rtile_load<RANK, VEC>(F[fb], tb - F[fb].wg_base, B);
+        if (tn < n_tiles) rtile_load<RANK, VEC>(F[fb], tb - F[fb].wg_base, B);
         {
             const FieldDesc& fd = F[fa];
             const auto* dy = kconst(fd.dyn);
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
         tn = t + gridDim.x;
         const uint32_t ta = tn < n_tiles ? tn : t;
         fa = find_field<&FieldDesc::wg_base>(F, nf, ta);
-        rtile_load<RANK, VEC>(F[fa], ta - F[fa].wg_base, A);
+        if (tn < n_tiles) rtile_load<RANK, VEC>(F[fa], ta - F[fa].wg_base, A);
         {
             const FieldDesc& fd = F[fb];
             const auto* dy = kconst(fd.dyn);
@@ -287,6 +287,101 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
         if (t >= n_tiles) break;
     }
     if (cur >= 0) flush_zeros(F[cur], zeros, s_z);
+}
+
+// 3D: a wave owns 256 x (one quad per lane) by one 8x8 chunk layer in y and
+// z; a workgroup stacks four waves along y (tile 256 x 32 x 8; the field
+// descriptor's nxb/nyb/nzb hold this tiling during decompression).  Per z
+// plane a lane holds its quad in each of the 8 rows of the chunk layer: the x
+// pass is in-lane plus the total of the pair lane (an 8-wide chunk row is two
+// quads), the y pass a running sum over the rows and the z pass a running sum
+// over the planes, both in registers.  Every row is one 512-byte code load
+// and one 1 KiB store per wave.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __restrict__ F, int nf)
+{
+    __shared__ uint32_t s_z[kWavesPerBlock];
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const auto* dy = kconst(fd.dyn);
+    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
+    const uint32_t tl = t - fd.wg_base;
+    const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+    const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+    const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+    const int l = lane_id();
+    const uint32_t w = threadIdx.x / kWave;
+    const uint32_t x0 = xb * 256 + 4 * l, y0 = yb * 32 + w * 8, z0 = zb * 8;
+    const int nvx = x0 < nx ? (int)min<uint32_t>(4, nx - x0) : 0;
+    const int32_t r = (int32_t)(fd.n_bins / 2);
+    const double ebx2 = dy->ebx2;
+    const EBC_G uint16_t* __restrict__ q = fd.q;
+    const EBC_G int32_t* __restrict__ dsc = fd.dsc;
+    EBC_G float* __restrict__ out = fd.outf;
+    uint32_t zeros = 0;
+    uint32_t zprev[8][4];
+#pragma unroll
+    for (int y = 0; y < 8; ++y)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zprev[y][k] = 0;
+    // planes of codes: the next one in flight while this one is processed
+    // (unrolled, so only those two occupy registers)
+    u32x2 raw[8][8];
+    auto load_plane = [&](int iz) {
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            const bool ok = y0 + y < ny && z0 + iz < nz && nvx > 0;
+            const uint64_t i0 = ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0;
+            if (VEC) raw[iz][y] = ld_nt_u2(q + (ok ? i0 : 0));
+            else raw[iz][y] = load_packed<false>(q, i0, ok ? nvx : 0);
+        }
+    };
+    load_plane(0);
+#pragma unroll
+    for (int iz = 0; iz < 8; ++iz) {
+        if (iz + 1 < 8) load_plane(iz + 1);
+        uint32_t yprev[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int y = 0; y < 8; ++y) {
+            const bool ok = y0 + y < ny && z0 + iz < nz;
+            const int nv = ok ? nvx : 0;
+            const uint64_t i0 = ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0;
+            uint32_t c[4], sv[4];
+            unpack4(raw[iz][y], c);
+            if (VEC) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (j >= nv) c[j] = 1u;  // absent: never the outlier placeholder
+            }
+            fuse4(c, nv, r, dsc, i0, sv, zeros);
+            sv[1] += sv[0], sv[2] += sv[1], sv[3] += sv[2];  // x pass within the quad
+            uint32_t left = dpp_shr_u<1>(sv[3]);            // the pair lane's total
+            if ((l & 1) == 0) left = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sv[k] += left;
+                sv[k] += yprev[k];  // y pass
+                yprev[k] = sv[k];
+                sv[k] += zprev[y][k];  // z pass
+                zprev[y][k] = sv[k];
+            }
+            float v[4];
+            dequant4(sv, ebx2, v);
+            if (VEC) {
+                st_nt_f4(nv == 4 ? out + i0 : fd.sink, f32x4{v[0], v[1], v[2], v[3]});
+            } else {
+                store_quad<false>(out, i0, nv, v);
+            }
+        }
+    }
+    const uint32_t zs = wave_sum_u32(zeros);
+    if (l == 0) s_z[w] = zs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t z = s_z[0] + s_z[1] + s_z[2] + s_z[3];
+        if (z) atomicAdd((unsigned long long*)&fd.dyn->zero_count, (unsigned long long)z);
+    }
 }
 
 // decompression epilogue: the code-0 count must equal the outlier count
@@ -340,8 +435,8 @@ uint32_t reconstruct_resident_blocks(int rank, bool vec)
         e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, true>, kBlock, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, false>, kBlock, 0);
     else
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<3, true>, kBlock, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<3, false>, kBlock, 0);
+        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct3<true>, kBlock, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct3<false>, kBlock, 0);
     if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
     return (uint32_t)(per * cus);
 }
@@ -358,8 +453,9 @@ hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, ui
         if (vec) hipLaunchKernelGGL((k_reconstruct<2, true>), g, b, 0, s, F, nf, wg_tiles);
         else hipLaunchKernelGGL((k_reconstruct<2, false>), g, b, 0, s, F, nf, wg_tiles);
     } else {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<3, true>), g, b, 0, s, F, nf, wg_tiles);
-        else hipLaunchKernelGGL((k_reconstruct<3, false>), g, b, 0, s, F, nf, wg_tiles);
+        const dim3 g3(wg_tiles);  // one workgroup per tile
+        if (vec) hipLaunchKernelGGL((k_reconstruct3<true>), g3, b, 0, s, F, nf);
+        else hipLaunchKernelGGL((k_reconstruct3<false>), g3, b, 0, s, F, nf);
     }
     return hipGetLastError();
 }

@@ -99,6 +99,9 @@ typedef struct ebc_stats {
     uint32_t n_stages;   /* out: number of valid stage_ms / stage_name entries */
     float stage_ms[EBC_MAX_STAGES];           /* out: per-stage kernel time (TIMING) */
     const char* stage_name[EBC_MAX_STAGES];   /* out: static strings */
+    const char* time_only; /* in: with TIMING, NULL times every stage; else only the stage
+                              of this name gets an event pair (one stage reported), so
+                              that the rest of the call runs uninstrumented */
 } ebc_stats;
 
 /* Library version (EBC_VERSION) and a static string for a status code. */

@@ -227,7 +227,7 @@ struct Batch {
     };
     std::vector<Group> groups;
     uint32_t tot_range = 0, tot_seg = 0, tot_ow = 0, tot_hch = 0, tot_hwg = 0, tot_hdwg = 0,
-             tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0;
+             tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0, tot_fx = 0;
     uint32_t max_rle_units = 0;
     FieldDesc* d_fd = nullptr;
     FieldDyn* d_dyn = nullptr;
@@ -386,10 +386,21 @@ struct Timer {
     std::vector<hipEvent_t> ev;
     std::vector<const char*> names;
     bool on;
-    Timer(ebc_stats* st_, hipStream_t s_) : st(st_), s(s_), on(st_ && (st_->flags & EBC_STATS_TIMING)) {}
+    const char* only = nullptr;  // time just this stage
+    bool in_only = false;
+    Timer(ebc_stats* st_, hipStream_t s_) : st(st_), s(s_), on(st_ && (st_->flags & EBC_STATS_TIMING))
+    {
+        if (on) only = st->time_only;
+    }
     void mark(const char* name)
     {
         if (!on || names.size() >= EBC_MAX_STAGES) return;
+        if (only) {
+            // the event after the chosen stage closes it; nothing else is recorded
+            const bool hit = strcmp(name, only) == 0;
+            if (!hit && !in_only) return;
+            in_only = hit;
+        }
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return;
         (void)hipEventRecord(e, s);
@@ -595,7 +606,7 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
     // per-codec unit counts (other codecs get zero units)
-    B.tot_hch = B.tot_hdwg = B.tot_rt = B.tot_runs = B.tot_sc = B.tot_rl = 0;
+    B.tot_hch = B.tot_hdwg = B.tot_rt = B.tot_runs = B.tot_sc = B.tot_rl = B.tot_fx = 0;
     B.tot_range = 0;
     for (int k = 0; k < B.nf; ++k) {
         const DecompressIn& D = din[B.order[k]];
@@ -612,6 +623,9 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.rl_base = B.tot_rl, d.rl_units = cdiv(d.n_runs_hdr, kBlock), B.tot_rl += d.rl_units;
         const uint32_t sc = cst ? 0 : cdiv(H.n_out, kBlock);
         d.sc_base = B.tot_sc, d.sc_units = sc, B.tot_sc += sc;
+        // 3D: at most one fix-up chunk per outlier, a wave each
+        const uint32_t fx = (cst || H.rank != 3) ? 0 : cdiv(H.n_out, kWavesPerBlock);
+        d.fx_base = B.tot_fx, d.fx_units = fx, B.tot_fx += fx;
         d.range_base = B.tot_range, d.range_units = cst ? g.range_units : 0, B.tot_range += d.range_units;
         if (cst) {
             // no reconstruction work for a constant field
@@ -672,8 +686,34 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.q = bp.take<uint16_t>(cst ? 0 : 2 * g.n);
         d.dsc = bp.take<int32_t>(cst ? 0 : 4 * g.n);
         d.sink = bp.take<float>(256);
+        const bool r3 = g.rank == 3 && !cst;
+        d.oflag = bp.take<uint32_t>(r3 ? 4ull * d.nxb * d.nyb * kWavesPerBlock * d.nzb : 0);
+        d.fixl = bp.take<uint32_t>(r3 ? 4ull * H.n_out : 0);
     }
     B.ws_bytes = bp.off;
+}
+
+// Outlier scatter and reconstruction.  The 3D reconstruction reads no
+// deltas and clears the chunk flags, so it runs before the scatter, which
+// queues the chunks holding outliers for the fix-up; 1D/2D reconstruction
+// fuses the scattered deltas itself.
+int enqueue_reconstruct(Batch& B, hipStream_t s, Timer& T)
+{
+    bool has3 = false, has12 = false;
+    for (const auto& G : B.groups) (G.rank == 3 ? has3 : has12) |= G.wg_tiles > 0;
+    if (has3) T.mark("reconstruct");
+    for (const auto& G : B.groups)
+        if (G.rank == 3)
+            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+    if (B.tot_sc) T.mark("outlier_scatter");
+    HIP_TRY(launch_outlier_scatter(B.d_fd, B.nf, B.tot_sc, s));
+    if (has12) T.mark(has3 ? "reconstruct_12" : "reconstruct");
+    for (const auto& G : B.groups)
+        if (G.rank != 3)
+            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+    if (B.tot_fx) T.mark("outlier_fix");
+    HIP_TRY(launch_recon_fix(B.d_fd, B.nf, B.tot_fx, s));
+    return EBC_OK;
 }
 
 int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
@@ -695,11 +735,8 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
         T.mark("rle_decode");
         HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmp, B.tot_runs, s));
     }
-    T.mark("outlier_scatter");
-    HIP_TRY(launch_outlier_scatter(B.d_fd, nf, B.tot_sc, s));
-    T.mark("reconstruct");
-    for (const auto& G : B.groups)
-        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+    const int st = enqueue_reconstruct(B, s, T);
+    if (st) return st;
     T.mark("check");
     HIP_TRY(launch_recon_check(B.d_fd, nf, s));
     HIP_TRY(launch_fill_const(B.d_fd, nf, B.tot_range, s));
@@ -1226,9 +1263,9 @@ int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int
     d.n_hch = 0, d.hdwg_units = 0;  // no entropy decoding
     HIP_TRY(upload_descs(B.fd.data(), 1, B.d_fd, s));
     HIP_TRY(launch_dinit(B.d_fd, 1, s));
-    HIP_TRY(launch_outlier_scatter(B.d_fd, 1, B.tot_sc, s));
-    for (const auto& G : B.groups)
-        HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+    Timer T(nullptr, s);
+    st = enqueue_reconstruct(B, s, T);
+    if (st) return st;
     HIP_TRY(launch_recon_check(B.d_fd, 1, s));
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);

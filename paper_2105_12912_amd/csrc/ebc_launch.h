@@ -62,6 +62,7 @@ hipError_t launch_outlier_scatter(const FieldDesc* F, int nf, uint32_t units, hi
 uint32_t reconstruct_resident_blocks(int rank, bool vec);
 hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
                               uint32_t blocks, hipStream_t s);
+hipError_t launch_recon_fix(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 hipError_t launch_recon_check(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_dinit(const FieldDesc* F, int nf, hipStream_t s);
 hipError_t launch_fill_const(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);

@@ -65,7 +65,9 @@ struct FieldDyn {
     uint32_t max_len;
     uint32_t n_used;  // symbols with a non-zero count
     uint64_t zero_count;
-    uint64_t pad[2];
+    uint32_t fix_count;  // decompress 3D: chunks queued for the outlier fix-up
+    uint32_t pad0;
+    uint64_t pad[1];
 };
 
 // Static description of one field: geometry, buffers, work bases.
@@ -103,6 +105,8 @@ struct FieldDesc {
     EBC_G uint8_t* len;      // n_bins code lengths
     EBC_G uint32_t* hbits;   // per Huffman chunk bit counts
     EBC_G uint32_t* rstart;  // RLE run starts (compress scratch)
+    EBC_G uint32_t* oflag;   // decompress 3D: per wave block, a bit per 8-wide x chunk with outliers
+    EBC_G uint32_t* fixl;    // decompress 3D: an outlier index in each flagged chunk (n_out)
     EBC_G FieldDyn* dyn;
     // this field's work units in each batch-wide index space
     uint32_t range_units, range_base;  // value range / fill: kRangeUnit elements per WG
@@ -116,6 +120,7 @@ struct FieldDesc {
     uint32_t n_runs_hdr, rle_base;     // decompress: runs in the archive (start array entries)
     uint32_t sc_units, sc_base;        // decompress outlier scatter: 256 outliers per WG
     uint32_t rl_units, rl_base;        // decompress run-length prep: 256 runs per WG
+    uint32_t fx_units, fx_base;        // decompress 3D outlier fix-up: 4 chunks per WG
     // decompress: header values
     uint64_t n_out_hdr;
     uint64_t n_words_hdr;

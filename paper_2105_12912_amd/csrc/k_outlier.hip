@@ -8,7 +8,8 @@
 // outliers of every row segment (the x-extent of one construct wave-tile);
 // after a scan of those counts, each segment with outliers is compacted by
 // one wavefront with ballot ranks.  Decompression scatters the list into a
-// dense delta scratch and validates it against the codes.
+// dense delta scratch, validates it against the codes and, for 3D fields,
+// queues the chunks that hold outliers for the reconstruction fix-up.
 #include "ebc_dev.h"
 #include "ebc_launch.h"
 
@@ -98,6 +99,17 @@ __global__ __launch_bounds__(kBlock) void k_outlier_scatter(const FieldDesc* __r
         return;
     }
     fd.dsc[i] = oval[k];
+    if (fd.rank == 3) {
+        // queue this outlier's 8x8x8 chunk for the reconstruction fix-up,
+        // once: the first outlier to set the chunk's flag appends it (the
+        // flags were cleared by the reconstruction, which ran before)
+        const uint32_t nx = fd.nx, ny = fd.ny;
+        const uint32_t x = i % nx, yz = i / nx;
+        const uint32_t y = yz % ny, z = yz / ny;
+        const uint32_t wb = ((z >> 3) * (fd.nyb * kWavesPerBlock) + (y >> 3)) * fd.nxb + (x >> 8);
+        const uint32_t bit = 1u << ((x & 255) >> 3);
+        if ((atomicOr(&fd.oflag[wb], bit) & bit) == 0) fd.fixl[atomicAdd(&dy->fix_count, 1u)] = i;
+    }
 }
 
 hipError_t launch_outlier_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* soff,

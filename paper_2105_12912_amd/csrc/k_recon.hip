@@ -289,72 +289,75 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
     if (cur >= 0) flush_zeros(F[cur], zeros, s_z);
 }
 
-// 3D: a wave owns 256 x (one quad per lane) by one 8x8 chunk layer in y and
-// z; a workgroup stacks four waves along y (tile 256 x 32 x 8; the field
-// descriptor's nxb/nyb/nzb hold this tiling during decompression).  Per z
-// plane a lane holds its quad in each of the 8 rows of the chunk layer: the x
-// pass is in-lane plus the total of the pair lane (an 8-wide chunk row is two
-// quads), the y pass a running sum over the rows and the z pass a running sum
-// over the planes, both in registers.  Every row is one 512-byte code load
-// and one 1 KiB store per wave.
-template <bool VEC>
-__global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __restrict__ F, int nf)
+// Bit 15 (bit 31) set iff the low (high) 16-bit code packed in w is 0: with
+// each half's top bit forced on, subtracting 1 clears it only in a half that
+// was 0, and never borrows across halves (codes are below 2^15).
+__device__ __forceinline__ uint32_t zero_half(uint32_t w)
 {
-    __shared__ uint32_t s_z[kWavesPerBlock];
-    const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
-    const FieldDesc& fd = F[f];
-    const auto* dy = kconst(fd.dyn);
-    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
-    const uint32_t tl = t - fd.wg_base;
-    const uint32_t nxb = fd.nxb, nyb = fd.nyb;
-    const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
-    const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+    return ~((w | 0x80008000u) - 0x00010001u) & 0x80008000u;
+}
+
+// Chunk rows of one wave of the 3D reconstruction (see k_reconstruct3).
+// FULL: the wave's 256 x 8 x 8 block lies inside the field and its rows are
+// 16-byte aligned, so every row is one load and one store with no per-lane or
+// per-row condition, addressed as a wave-uniform row pointer plus the lane's
+// offset.  Otherwise rows outside the field are skipped, absent codes read as
+// 1 and absent elements are not stored.  Outlier codes (0) enter as 0 - r
+// and are only counted here: k_recon3_fix rewrites every chunk that holds
+// one.
+template <bool FULL, bool VEC>
+__device__ __forceinline__ void recon3_wave(const FieldDesc& fd, uint32_t x0w, uint32_t y0, uint32_t z0,
+                                            double ebx2, uint32_t& zeros)
+{
     const int l = lane_id();
-    const uint32_t w = threadIdx.x / kWave;
-    const uint32_t x0 = xb * 256 + 4 * l, y0 = yb * 32 + w * 8, z0 = zb * 8;
+    const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+    const uint32_t x0 = x0w + 4 * l;
     const int nvx = x0 < nx ? (int)min<uint32_t>(4, nx - x0) : 0;
-    const int32_t r = (int32_t)(fd.n_bins / 2);
-    const double ebx2 = dy->ebx2;
+    const uint32_t r = fd.n_bins / 2;
     const EBC_G uint16_t* __restrict__ q = fd.q;
-    const EBC_G int32_t* __restrict__ dsc = fd.dsc;
     EBC_G float* __restrict__ out = fd.outf;
-    uint32_t zeros = 0;
+    // wave-uniform first element of row y of plane iz (x = x0w)
+    auto row = [&](int iz, int y) -> uint64_t { return ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0w; };
+    auto row_ok = [&](int iz, int y) -> bool { return FULL || (y0 + y < ny && z0 + iz < nz); };
     uint32_t zprev[8][4];
 #pragma unroll
     for (int y = 0; y < 8; ++y)
 #pragma unroll
         for (int k = 0; k < 4; ++k) zprev[y][k] = 0;
     // planes of codes: the next one in flight while this one is processed
-    // (unrolled, so only those two occupy registers)
+    // (fully unrolled, so only those two occupy registers)
     u32x2 raw[8][8];
     auto load_plane = [&](int iz) {
 #pragma unroll
         for (int y = 0; y < 8; ++y) {
-            const bool ok = y0 + y < ny && z0 + iz < nz && nvx > 0;
-            const uint64_t i0 = ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0;
-            if (VEC) raw[iz][y] = ld_nt_u2(q + (ok ? i0 : 0));
-            else raw[iz][y] = load_packed<false>(q, i0, ok ? nvx : 0);
+            if (FULL) {
+                raw[iz][y] = *(const EBC_G u32x2*)(q + row(iz, y) + 4 * l);
+            } else {
+                const bool ok = row_ok(iz, y);
+                raw[iz][y] = load_packed<VEC>(q, ok ? row(iz, y) + 4 * l : 0, ok ? nvx : 0);
+            }
         }
     };
     load_plane(0);
 #pragma unroll
     for (int iz = 0; iz < 8; ++iz) {
+        // keep the schedule at one plane of loads ahead: without this fence
+        // the compiler hoists every plane's loads and runs out of registers
+        __builtin_amdgcn_sched_barrier(0);
         if (iz + 1 < 8) load_plane(iz + 1);
         uint32_t yprev[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int y = 0; y < 8; ++y) {
-            const bool ok = y0 + y < ny && z0 + iz < nz;
-            const int nv = ok ? nvx : 0;
-            const uint64_t i0 = ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0;
+            if (!FULL && !row_ok(iz, y)) continue;  // wave-uniform
             uint32_t c[4], sv[4];
-            unpack4(raw[iz][y], c);
-            if (VEC) {
+            const u32x2 t = raw[iz][y];
+            unpack4(t, c);
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (j >= nv) c[j] = 1u;  // absent: never the outlier placeholder
-            }
-            fuse4(c, nv, r, dsc, i0, sv, zeros);
+            for (int k = 0; k < 4; ++k) sv[k] = c[k] - r;
+            zeros += __builtin_popcount(zero_half(t.x)) + __builtin_popcount(zero_half(t.y));
+            // accumulate in place: a reassociated sum would hold every
+            // row's count in a register of its own until the end
+            asm volatile("" : "+v"(zeros));
             sv[1] += sv[0], sv[2] += sv[1], sv[3] += sv[2];  // x pass within the quad
             uint32_t left = dpp_shr_u<1>(sv[3]);            // the pair lane's total
             if ((l & 1) == 0) left = 0;
@@ -368,20 +371,120 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __rest
             }
             float v[4];
             dequant4(sv, ebx2, v);
-            if (VEC) {
-                st_nt_f4(nv == 4 ? out + i0 : fd.sink, f32x4{v[0], v[1], v[2], v[3]});
+            if (FULL) {
+                st_nt_f4(out + row(iz, y) + 4 * l, f32x4{v[0], v[1], v[2], v[3]});
             } else {
-                store_quad<false>(out, i0, nv, v);
+                store_quad<VEC>(out, row(iz, y) + 4 * l, nvx, v);
             }
         }
     }
+}
+
+// 3D: a wave owns 256 x (one quad per lane) by one 8x8 chunk layer in y and
+// z; a workgroup stacks four waves along y (tile 256 x 32 x 8; the field
+// descriptor's nxb/nyb/nzb hold this tiling during decompression).  Per z
+// plane a lane holds its quad in each of the 8 rows of the chunk layer: the x
+// pass is in-lane plus the total of the pair lane (an 8-wide chunk row is two
+// quads), the y pass a running sum over the rows and the z pass a running sum
+// over the planes, both in registers.  Every row is one 512-byte code load
+// and one 1 KiB store per wave.
+//
+// Outliers are not read here: a wait for a delta loaded in the middle of the
+// stream would also wait for every load and store issued before it.  Instead
+// each wave clears its block's chunk flags, which the outlier scatter sets
+// afterwards, and k_recon3_fix recomputes the flagged chunks exactly.
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __restrict__ F, int nf)
+{
+    __shared__ uint32_t s_z[kWavesPerBlock];
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const auto* dy = kconst(fd.dyn);
+    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
+    const uint32_t tl = t - fd.wg_base;
+    const uint32_t nxb = fd.nxb, nyb = fd.nyb;
+    const uint32_t xb = tl % nxb, yb = (tl / nxb) % nyb, zb = tl / (nxb * nyb);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const uint32_t x0w = xb * 256, y0 = yb * 32 + w * 8, z0 = zb * 8;
+    const double ebx2 = dy->ebx2;
+    uint32_t zeros = 0;
+    if (lane_id() == 0) fd.oflag[(zb * (nyb * kWavesPerBlock) + yb * kWavesPerBlock + w) * nxb + xb] = 0;
+    if (VEC && x0w + 256 <= fd.nx && y0 + 8 <= fd.ny && z0 + 8 <= fd.nz)
+        recon3_wave<true, VEC>(fd, x0w, y0, z0, ebx2, zeros);
+    else
+        recon3_wave<false, VEC>(fd, x0w, y0, z0, ebx2, zeros);
     const uint32_t zs = wave_sum_u32(zeros);
-    if (l == 0) s_z[w] = zs;
+    if (lane_id() == 0) s_z[w] = zs;
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t z = s_z[0] + s_z[1] + s_z[2] + s_z[3];
         if (z) atomicAdd((unsigned long long*)&fd.dyn->zero_count, (unsigned long long)z);
     }
+}
+
+// Outlier fix-up of the 3D reconstruction: one wave per 8x8x8 chunk that
+// holds an outlier (queued by the outlier scatter), recomputed from its codes
+// with the exact deltas substituted.  Lane (yl, zl) = (l % 8, l / 8) owns the
+// chunk row of 8 x; the x pass is in-lane, the y pass a scan over the 8 lanes
+// of a z layer and the z pass a scan over the 8 layers.  Elements outside
+// the field enter as 0 and are not stored.
+__global__ __launch_bounds__(kBlock) void k_recon3_fix(const FieldDesc* __restrict__ F, int nf)
+{
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::fx_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    const auto* dy = kconst(fd.dyn);
+    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
+    const uint32_t g = (t - fd.fx_base) * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // the queue entry is fetched alongside the count (clamped into the queue)
+    const uint32_t cnt = dy->fix_count;
+    const uint64_t i = kconst(fd.fixl)[min<uint64_t>(g, fd.n_out_hdr - 1)];
+    if (g >= cnt) return;
+    const uint32_t nx = fd.nx, ny = fd.ny, nz = fd.nz;
+    const uint32_t cx = (uint32_t)(i % nx) & ~7u;
+    const uint64_t yz = i / nx;
+    const uint32_t cy = (uint32_t)(yz % ny) & ~7u, cz = (uint32_t)(yz / ny) & ~7u;
+    const int l = lane_id();
+    const uint32_t yl = l & 7, zl = l >> 3;
+    const uint32_t yy = cy + yl, zz = cz + zl;
+    const bool ok = yy < ny && zz < nz;
+    const uint32_t nv = ok ? min<uint32_t>(8, nx - cx) : 0;
+    const uint64_t i0 = ok ? ((uint64_t)zz * ny + yy) * nx + cx : 0;
+    const uint32_t r = fd.n_bins / 2;
+    // codes and deltas loaded together (one round trip)
+    uint32_t c[8], dv[8], sv[8];
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e) {
+        c[e] = 1, dv[e] = 0;
+        if (e < nv) c[e] = fd.q[i0 + e], dv[e] = (uint32_t)fd.dsc[i0 + e];
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e) sv[e] = e < nv ? (c[e] == 0 ? dv[e] : c[e] - r) : 0u;
+#pragma unroll
+    for (int e = 1; e < 8; ++e) sv[e] += sv[e - 1];  // x pass
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        // y pass: inclusive scan over the 8 lanes of this z layer
+        uint32_t a = dpp_shr_u<1>(sv[e]);
+        sv[e] += yl >= 1 ? a : 0u;
+        a = dpp_shr_u<2>(sv[e]);
+        sv[e] += yl >= 2 ? a : 0u;
+        a = dpp_shr_u<4>(sv[e]);
+        sv[e] += yl >= 4 ? a : 0u;
+        // z pass: inclusive scan over the 8 layers (lane strides of 8)
+        a = (uint32_t)__shfl_up((int)sv[e], 8);
+        sv[e] += zl >= 1 ? a : 0u;
+        a = (uint32_t)__shfl_up((int)sv[e], 16);
+        sv[e] += zl >= 2 ? a : 0u;
+        a = (uint32_t)__shfl_up((int)sv[e], 32);
+        sv[e] += zl >= 4 ? a : 0u;
+    }
+    const double ebx2 = dy->ebx2;
+    EBC_G float* __restrict__ out = fd.outf;
+#pragma unroll
+    for (uint32_t e = 0; e < 8; ++e)
+        if (e < nv) out[i0 + e] = (float)((double)(int32_t)sv[e] * ebx2);
 }
 
 // decompression epilogue: the code-0 count must equal the outlier count
@@ -457,6 +560,13 @@ hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, ui
         if (vec) hipLaunchKernelGGL((k_reconstruct3<true>), g3, b, 0, s, F, nf);
         else hipLaunchKernelGGL((k_reconstruct3<false>), g3, b, 0, s, F, nf);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_recon_fix(const FieldDesc* F, int nf, uint32_t units, hipStream_t s)
+{
+    if (!units) return hipSuccess;
+    hipLaunchKernelGGL(k_recon3_fix, dim3(units), dim3(kBlock), 0, s, F, nf);
     return hipGetLastError();
 }
 

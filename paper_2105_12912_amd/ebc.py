@@ -45,7 +45,7 @@ class ebc_stats(C.Structure):
                 ("huff_bits", C.c_uint64), ("out_bytes", C.c_uint64), ("eb_abs", C.c_double),
                 ("ebx2", C.c_double), ("value_min", C.c_float), ("value_max", C.c_float),
                 ("n_stages", C.c_uint32), ("stage_ms", C.c_float * EBC_MAX_STAGES),
-                ("stage_name", C.c_char_p * EBC_MAX_STAGES)]
+                ("stage_name", C.c_char_p * EBC_MAX_STAGES), ("time_only", C.c_char_p)]
 
     def stages(self) -> dict:
         return {self.stage_name[k].decode(): float(self.stage_ms[k]) for k in range(self.n_stages)}
@@ -357,7 +357,7 @@ def field_rank_dims(x, rank: int | None = None):
 
 
 def compress(x, eb: float, mode: str = "rel", n_bins: int = 1024, codec: str = "auto",
-             huff_chunk: int = 1024, stream=None, stats: bool = False, workspace=None,
+             huff_chunk: int = 1024, stream=None, stats: bool | str = False, workspace=None,
              out=None):
     """Compress a contiguous fp32 CUDA tensor; returns a uint8 CUDA tensor (and stats)."""
     torch = _torch()
@@ -371,7 +371,7 @@ def compress(x, eb: float, mode: str = "rel", n_bins: int = 1024, codec: str = "
     wptr, wlen = ws.get(wsz)
     if out is None or out.numel() < bound:
         out = torch.empty(bound, dtype=torch.uint8, device=x.device)
-    st_obj = ebc_stats(flags=EBC_STATS_TIMING) if stats else None
+    st_obj = _stats_obj(stats)
     st, size = ebc_compress(x.data_ptr(), rank, dims, p, out.data_ptr(), out.numel(), wptr, wlen,
                             _stream_handle(stream), st_obj)
     _check(st, "ebc_compress")
@@ -379,11 +379,22 @@ def compress(x, eb: float, mode: str = "rel", n_bins: int = 1024, codec: str = "
     return (a, st_obj) if stats else a
 
 
+def _stats_obj(stats):
+    """stats: False (none), True (time every stage) or a stage name (time only it)."""
+    if not stats:
+        return None
+    st = ebc_stats(flags=EBC_STATS_TIMING)
+    if isinstance(stats, str):
+        st._only = stats.encode()  # keeps the string alive for the call
+        st.time_only = st._only
+    return st
+
+
 def archive_header(a) -> bytes:
     return bytes(a[:HDR_BYTES].cpu().numpy().tobytes())
 
 
-def decompress(a, out=None, stream=None, stats: bool = False, workspace=None):
+def decompress(a, out=None, stream=None, stats: bool | str = False, workspace=None):
     """Decompress a uint8 CUDA archive tensor into a float32 CUDA tensor."""
     torch = _torch()
     hdr = archive_header(a)
@@ -395,7 +406,7 @@ def decompress(a, out=None, stream=None, stats: bool = False, workspace=None):
     wsz = ebc_decompress_workspace_size(hdr)
     ws = workspace or default_workspace(a.device)
     wptr, wlen = ws.get(wsz)
-    st_obj = ebc_stats(flags=EBC_STATS_TIMING) if stats else None
+    st_obj = _stats_obj(stats)
     st = ebc_decompress(a.data_ptr(), a.numel(), out.data_ptr(), out.numel(), wptr, wlen,
                         _stream_handle(stream), st_obj)
     _check(st, "ebc_decompress")

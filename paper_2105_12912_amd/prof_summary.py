@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = {
     "k_construct": ["paper_2105_12912_amd/csrc/k_quant.hip"],
     "k_reconstruct": ["paper_2105_12912_amd/csrc/k_recon.hip"],
+    "k_reconstruct3": ["paper_2105_12912_amd/csrc/k_recon.hip"],
     "k_huff_decode": ["paper_2105_12912_amd/csrc/k_huffman.hip"],
     "k_huff_write": ["paper_2105_12912_amd/csrc/k_huffman.hip"],
     "k_huff_bits": ["paper_2105_12912_amd/csrc/k_huffman.hip"],

@@ -224,3 +224,71 @@ def test_full_size_2d_bytes(E):
         assert a.cpu().numpy().tobytes() == ref
         y = E.decompress(a)
         np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(O.decompress(ref)))
+
+
+def test_3d_dense_outliers(E):
+    """Almost every delta out of range (4 bins): every 8x8x8 chunk, including
+    the ragged ones on all three far faces, goes through the outlier fix-up."""
+    for shape in [(19, 23, 41), (8, 8, 256)]:
+        x = rng_field(shape, 21, "noise")
+        ref = O.compress(x, 1e-3, n_bins=4)
+        info = O.archive_info(ref)
+        assert info["n_outliers"] > x.size // 2
+        a = E.compress(dev(x), 1e-3, n_bins=4)
+        assert a.cpu().numpy().tobytes() == ref
+        y = E.decompress(a)
+        np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(O.decompress(ref)))
+
+
+def test_3d_corrupt_outlier_rejected(E):
+    """A 3D outlier index moved onto a non-placeholder code is rejected."""
+    x = rng_field((24, 40, 33), 25, "lognormal")
+    raw = E.compress(dev(x), 1e-4).cpu().numpy().copy()
+    s = O.sections(raw.tobytes())
+    info = s["info"]
+    assert info["n_outliers"] > 0
+    nch, nw = info["n_a"], info["n_words"]
+    ob = (128 + info["n_bins"] + 15) & ~15
+    ow = (ob + 4 * nch + 15) & ~15
+    oo = (ow + 4 * nw + 15) & ~15
+    it = O.intermediates(x, 1e-4)
+    nz = int(np.flatnonzero(it["q"].ravel() != 0)[0])
+    b = raw.copy()
+    b[oo:oo + 4] = np.frombuffer(np.uint32(nz).tobytes(), np.uint8)
+    assert O.decompress_status(b.tobytes()) == -9
+    assert E.decompress_status(dev(b)) == E.EBC_ERR_ARCHIVE
+
+
+def test_stage_timing_options(E):
+    """Every stage timed, or only the named one (one event pair)."""
+    x = dev(rng_field((24, 40, 33), 25, "lognormal"))
+    a, cs = E.compress(x, 1e-4, stats=True)
+    y, ds = E.decompress(a, stats=True)
+    assert {"construct", "encode_write"} <= set(cs.stages())
+    assert {"huffman_decode", "reconstruct", "outlier_scatter", "outlier_fix"} <= set(ds.stages())
+    y2, d1 = E.decompress(a, stats="reconstruct")
+    st = d1.stages()
+    assert list(st) == ["reconstruct"] and st["reconstruct"] > 0
+    np.testing.assert_array_equal(bits(y2.cpu().numpy()), bits(y.cpu().numpy()))
+    _, c1 = E.compress(x, 1e-4, stats="construct")
+    assert list(c1.stages()) == ["construct"]
+
+
+def test_full_size_3d_bench_workload(E):
+    """The benchmark's 512^3 lognormal field at rel 1e-4, plain path with the
+    default tiling (the configuration the benchmark times): whole archive and
+    every reconstructed value equal to the oracle's."""
+    import bench
+
+    _, gen, eb = bench.WORKLOADS["nyx512"]
+    x = gen(synth)
+    print("[full-size 3d] oracle", flush=True)
+    ref = O.compress(x, eb)
+    want = O.decompress(ref)
+    print("[full-size 3d] gpu", flush=True)
+    xd = dev(x)
+    a = E.compress(xd, eb)
+    assert a.cpu().numpy().tobytes() == ref
+    del xd
+    y = E.decompress(a)
+    np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(want))

@@ -743,12 +743,43 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     return EBC_OK;
 }
 
+// Page-locked staging for the small device-to-host reads of the synchronous
+// entry points: a copy into it is one DMA ordered on the stream, where a copy
+// into pageable memory is staged by the runtime and starts late.  One buffer
+// per host thread, grown on demand and kept for the life of the thread; NULL
+// if page-locked memory is unavailable (the caller then reads into pageable
+// memory).
+void* pinned_stage(size_t bytes)
+{
+    thread_local void* p = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        const size_t want = std::max<size_t>(4096, (bytes + 4095) & ~size_t(4095));
+        void* q = nullptr;
+        if (hipHostMalloc(&q, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (p) (void)hipHostFree(p);
+        p = q, cap = want;
+    }
+    return p;
+}
+
+// Synchronous device-to-host read of a few bytes on stream s.
+int read_small(void* host, const void* dev, size_t bytes, hipStream_t s)
+{
+    void* stage = pinned_stage(bytes);
+    HIP_TRY(hipMemcpyAsync(stage ? stage : host, dev, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (stage) memcpy(host, stage, bytes);
+    return EBC_OK;
+}
+
 int read_dyn(const Batch& B, std::vector<FieldDyn>& dyn, hipStream_t s)
 {
     dyn.resize(B.nf);
-    HIP_TRY(hipMemcpyAsync(dyn.data(), B.d_dyn, sizeof(FieldDyn) * B.nf, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return EBC_OK;
+    return read_small(dyn.data(), B.d_dyn, sizeof(FieldDyn) * B.nf, s);
 }
 
 int status_of(const FieldDyn& d)
@@ -975,8 +1006,8 @@ int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t 
     if (!d_archive) return fail(EBC_ERR_ARG, "archive is NULL");
     if (size < kHdr) return fail(EBC_ERR_ARCHIVE, "archive shorter than its header");
     uint8_t hdr[kHdr];
-    HIP_TRY(hipMemcpyAsync(hdr, d_archive, kHdr, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    int st0 = read_small(hdr, d_archive, kHdr, s);
+    if (st0) return st0;
     Header H;
     int st = parse_header(hdr, kHdr, &H);
     if (st) return st;

@@ -33,7 +33,6 @@ constexpr uint32_t kPersistentBlocks = 1024; // grid size of the persistent (gri
 constexpr uint32_t kConstructBlocks = 2048;  // construction grid: 8 workgroups per CU
 constexpr int kLutBits = 12;                // Huffman decode table width (bits looked up at once)
 constexpr int kMaxDecodeLen = 60;          // longest code the decoder accepts (N < 2^32 gives <= 46)
-constexpr int kLongLens = 16;              // long-code lengths compared in registers
 constexpr uint32_t kL2Size = 2048;         // second-level decode table entries
 constexpr uint32_t kL2MaxBits = 8;         // bits a second-level table resolves at most
 

@@ -284,16 +284,19 @@ __device__ __forceinline__ uint64_t window_at(const EBC_G uint32_t* __restrict__
 
 // Per-lane ring of a stream's 32-bit words in LDS, in two halves.  The next
 // half (16-byte blocks) is always in flight in registers: at a wave-uniform
-// refill point, every kRefillEvery iterations, a lane whose reader has left
-// the older half writes the loaded half there and issues the loads of the
-// following one.  A load therefore has a whole refill period to land before
-// it is waited for, and bit refills read LDS only; a lane that outruns its
-// ring (runs of very long codes) reads global memory directly.
+// refill point, every kRefillEvery iterations, a lane whose reader has entered
+// the newer half writes the loaded half over the older one and issues the
+// loads of the following one.  A load therefore has a whole refill period to
+// land before it is waited for, and bit top-ups read LDS only.  The decode
+// loop consumes at most one word per iteration (codewords longer than 32 bits
+// leave it), so between two refill points a reader advances at most
+// kRefillEvery <= kHalfWords words and never leaves the ring.
 constexpr uint32_t kRingWords = 16;
 constexpr uint32_t kHalfWords = kRingWords / 2;
 constexpr uint32_t kHalfBlocks = kHalfWords / 4;
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: no bank conflicts across lanes
-constexpr uint32_t kRefillEvery = 16;             // iterations; at most 12 bits each from the table
+constexpr uint32_t kRefillEvery = 8;              // iterations (a power of two, <= kHalfWords)
+static_assert(kRefillEvery <= kHalfWords, "a reader must not outrun the ring between refills");
 
 struct WordRing {
     uint32_t* ring;                        // this lane's slots in LDS
@@ -311,17 +314,9 @@ struct WordRing {
         }
         return make_uint4(0u, 0u, 0u, 0u);
     }
-    // Stream word i.  The value always comes out of the ring slot, so the
-    // merge of the two paths waits on LDS only, never on the loads in flight;
-    // a lane that outran the ring first copies the word into the (consumed)
-    // slot.
-    __device__ __forceinline__ uint32_t get(uint32_t i)
-    {
-        const uint32_t a = i + o;
-        const uint32_t slot = a % kRingWords;
-        if (!(a < wr && a + kRingWords >= wr)) ring[slot] = i < nw ? words[i] : 0u;
-        return ring[slot];
-    }
+    // stream word rd (in the ring by the refill schedule); past the stream's
+    // end the slot holds zeros or stale words, which a valid stream never uses
+    __device__ __forceinline__ uint32_t peek() const { return ring[(rd + o) % kRingWords]; }
     __device__ __forceinline__ void put(uint32_t* d, uint4 v)
     {
         d[0] = v.x, d[1] = v.y, d[2] = v.z, d[3] = v.w;
@@ -342,7 +337,6 @@ struct WordRing {
         for (uint32_t k = 0; k < kHalfBlocks; ++k) p[k] = fetch(kRingWords / 4 + k);
         rd = 0;
     }
-    __device__ __forceinline__ uint32_t pop() { return get(rd++); }
     // wave-uniform refill point
     __device__ __forceinline__ void refill()
     {
@@ -399,8 +393,7 @@ struct SymAcc {
 // kLutBits + 1 plus the number of code-space ends the window lies at or above.
 // Returns the length (0 if the bits are not a codeword) and the symbol.
 struct LongCode {
-    const uint64_t* ev;  // ends of lengths kLutBits+1 .. kLutBits+kLongLens (wave-uniform)
-    uint32_t nlong, maxl;
+    uint32_t maxl;
     const uint64_t* s_endv;
     const uint64_t* s_first;
     const uint32_t* s_off;
@@ -408,15 +401,15 @@ struct LongCode {
     __device__ __forceinline__ uint32_t decode(uint64_t w, uint32_t& sym) const
     {
         uint32_t L = kLutBits + 1;
-#pragma unroll
-        for (int k = 0; k < kLongLens; ++k)
-            if ((uint32_t)k < nlong) L += w >= ev[k] ? 1u : 0u;
-        for (uint32_t l = kLutBits + 1 + kLongLens; l < maxl; ++l) L += w >= s_endv[l] ? 1u : 0u;
+        for (uint32_t l = kLutBits + 1; l < maxl; ++l) L += w >= s_endv[l] ? 1u : 0u;
         // the window is at or above the first length-L code by construction;
         // it must also be below the end of the length-L codes
         const uint64_t d = (w >> (64 - L)) - s_first[L];
         if (d >= (uint64_t)(s_off[L + 1] - s_off[L])) return 0;
         sym = perm[s_off[L] + (uint32_t)d];
+        // wait for the symbol here: where the paths merge, a wait would also
+        // cover every stream load and output store in flight
+        asm volatile("" ::"v"(sym));
         return L;
     }
 };
@@ -451,9 +444,6 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
         s_off[threadIdx.x] = T->offset[threadIdx.x];
     }
     const uint32_t maxl = T->max_len;
-    uint64_t ev[kLongLens];
-#pragma unroll
-    for (int k = 0; k < kLongLens; ++k) ev[k] = T->endv[kLutBits + 1 + k];
     __syncthreads();
     const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x / 2;
     const uint32_t half = threadIdx.x & 1;
@@ -486,97 +476,103 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
     const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + wo + w0;
     const uint32_t nwl = nw - w0;
     EBC_G uint16_t* __restrict__ out = fd.q + lo + s0;
-    const LongCode lc{ev, maxl > kLutBits + 1 ? maxl - kLutBits - 1 : 0u, maxl,
-                      s_endv, s_first, s_off, T->perm};
+    const LongCode lc{maxl, s_endv, s_first, s_off, T->perm};
 
     WordRing wr;
     wr.init(s_ring + threadIdx.x * kRingStride, words, nwl);
-    uint64_t buf = (uint64_t)wr.pop() << 32;
-    buf |= wr.pop();
+    uint64_t buf = (uint64_t)wr.peek() << 32;
+    ++wr.rd;
+    buf |= wr.peek();
+    ++wr.rd;
     // positions below are relative to word w0 of the chunk
     const uint32_t skip = b0 & 31;
     buf <<= skip;
-    uint32_t valid = 64 - skip, pos = skip, j = 0, it = 0;
-    bool bad = false;
+    uint32_t valid = 64 - skip, pos = skip, j = 0;
+    bool bad = false, slow = false;
     SymAcc acc;
-    // main loop: at least three symbols left, so whole table entries are used
-    while (j + 3 <= want) {
-        if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
-        if (valid < 32) {
-            buf |= (uint64_t)wr.pop() << (32 - valid);
-            valid += 32;
-        }
-        const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
-        uint32_t n = (uint32_t)(e >> 48) & 3u;
-        uint32_t tl = (uint32_t)(e >> 50) & 63u;
-        uint64_t syms = e & 0xFFFFFFFFFFFFull;
-        if (n == 0) {
-            // second level, then the canonical search for longer codewords
-            uint32_t sym = 0, L = 0;
-            const uint32_t base = (uint32_t)e & 0xFFFFu;
-            if (base != 0xFFFFu) {
-                const uint32_t v = l2s[base + (uint32_t)((buf << kLutBits) >> (64 - l2k))];
-                L = v >> 16;
-                sym = v & 0xFFFFu;
+    // Main loop: passes of kRefillEvery steps, each pass behind one refill
+    // point; the wave leaves when none of its lanes is still in the fast path.
+    // A step tops the buffer up to at least 32 bits (branch-free, with the
+    // next stream word already read from the ring one step ahead) and takes
+    // one table entry: up to three codewords, fewer at the end of the lane's
+    // symbols.  A lane out of the fast path (done, or moved to the exact path
+    // by a codeword longer than 32 bits) takes steps of zero codewords and
+    // zero bits, which change neither its position nor its output.
+    uint32_t nxt = wr.peek();
+    bool act = true;
+    while (__any(act)) {
+        wr.refill();
+        for (uint32_t u = 0; u < kRefillEvery; ++u) {
+            {
+                const bool need = valid < 32;
+                buf |= need ? ((uint64_t)nxt << ((32u - valid) & 63u)) : 0ull;
+                valid += need ? 32u : 0u;
+                wr.rd += need ? 1u : 0u;
+                nxt = wr.peek();
             }
-            if (L == 0) L = lc.decode(buf, sym);
-            if (L == 0 || L > valid) {
-                // longer than the buffered bits (only codes > 32 bits): exact window
-                L = lc.decode(window_at(words, nwl, pos), sym);
-                if (L == 0) {
-                    bad = true;
-                    break;
+            const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+            const uint32_t eh = (uint32_t)(e >> 32);
+            uint32_t n = (eh >> 16) & 3u;
+            uint32_t tl = (eh >> 18) & 63u;
+            uint64_t syms = e & 0xFFFFFFFFFFFFull;
+            if (act && n == 0) {
+                // second level, then the canonical search for longer codewords
+                uint32_t sym = 0, L = 0;
+                const uint32_t base = (uint32_t)e & 0xFFFFu;
+                if (base != 0xFFFFu) {
+                    const uint32_t v = l2s[base + (uint32_t)((buf << kLutBits) >> (64 - l2k))];
+                    L = v >> 16;
+                    sym = v & 0xFFFFu;
                 }
+                if (L == 0) L = lc.decode(buf, sym);
+                if (L == 0 || L > 32) {
+                    slow = true;
+                    act = false;
+                }
+                n = 1;
+                tl = L;
+                syms = sym;
             }
-            n = 1;
-            tl = L;
-            syms = sym;
-        }
-        acc.append(out, syms, n);
-        j += n;
-        pos += tl;
-        if (tl <= valid) {
+            // the lane's last symbols take only the leading codewords; a lane
+            // out of the fast path takes none
+            const uint32_t left = act ? want - j : 0u;
+            if (n > left) {
+                tl = left == 0 ? 0u : ((eh >> 24) & 15u) + (left == 2 ? eh >> 28 : 0u);
+                syms &= left == 0 ? 0ull : (left == 1 ? 0xFFFFull : 0xFFFFFFFFull);
+                n = left;
+            }
+            acc.append(out, syms, n);
+            j += n;
+            pos += tl;
             buf <<= tl;
             valid -= tl;
-        } else {
-            const uint32_t kk = pos >> 5, sh = pos & 31;
-            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << sh;
-            wr.rd = kk + 2;
-            valid = 64 - sh;
+            act = act && j < want;
         }
     }
-    // tail: one codeword at a time
-    while (!bad && j < want) {
-        if ((++it & (kRefillEvery - 1)) == 0) wr.refill();
-        if (valid < 32) {
-            buf |= (uint64_t)wr.pop() << (32 - valid);
-            valid += 32;
-        }
-        const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
+    // exact path, one codeword at a time from a window read straight from the
+    // stream (lanes that met a codeword longer than 32 bits)
+    while (slow && j < want) {
+        const uint64_t w = window_at(words, nwl, pos);
+        const uint64_t e = lut[(uint32_t)(w >> (64 - kLutBits))];
         uint32_t sym = (uint32_t)e & 0xFFFFu;
         uint32_t L = (uint32_t)(e >> 56) & 15u;
         if (((e >> 48) & 3u) == 0) {
-            L = lc.decode(buf, sym);
-            if (L == 0 || L > valid) {
-                L = lc.decode(window_at(words, nwl, pos), sym);
-                if (L == 0) {
-                    bad = true;
-                    break;
-                }
+            L = 0;
+            const uint32_t base = (uint32_t)e & 0xFFFFu;
+            if (base != 0xFFFFu) {
+                const uint32_t v = l2s[base + (uint32_t)((w << kLutBits) >> (64 - l2k))];
+                L = v >> 16;
+                sym = v & 0xFFFFu;
+            }
+            if (L == 0) L = lc.decode(w, sym);
+            if (L == 0) {
+                bad = true;
+                break;
             }
         }
         acc.append(out, sym, 1);
         j += 1;
         pos += L;
-        if (L <= valid) {
-            buf <<= L;
-            valid -= L;
-        } else {
-            const uint32_t kk = pos >> 5, sh = pos & 31;
-            buf = (((uint64_t)wr.get(kk) << 32) | wr.get(kk + 1)) << sh;
-            wr.rd = kk + 2;
-            valid = 64 - sh;
-        }
     }
     if (!bad) acc.flush(out);
     // the first half must end exactly at the midpoint, the second within the chunk

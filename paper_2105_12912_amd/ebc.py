@@ -15,6 +15,7 @@ call raises.  Build it with ``python -m paper_2105_12912_amd.build``.
 from __future__ import annotations
 
 import ctypes as C
+import threading
 import os
 import re
 
@@ -390,8 +391,23 @@ def _stats_obj(stats):
     return st
 
 
+_hdr_stage = threading.local()
+
+
 def archive_header(a) -> bytes:
-    return bytes(a[:HDR_BYTES].cpu().numpy().tobytes())
+    """The archive's 128-byte header, read through a page-locked buffer (a
+    direct copy on the current stream) when the archive is on the GPU."""
+    torch = _torch()
+    if not a.is_cuda:
+        return bytes(a[:HDR_BYTES].numpy().tobytes())
+    bufs = _hdr_stage.__dict__.setdefault("bufs", {})
+    buf = bufs.get(a.device)
+    if buf is None:
+        buf = bufs[a.device] = torch.empty(HDR_BYTES, dtype=torch.uint8, pin_memory=True)
+    n = min(HDR_BYTES, a.numel())
+    buf[:n].copy_(a[:n], non_blocking=True)
+    torch.cuda.current_stream(a.device).synchronize()
+    return bytes(buf[:n].numpy().tobytes())
 
 
 def decompress(a, out=None, stream=None, stats: bool | str = False, workspace=None):

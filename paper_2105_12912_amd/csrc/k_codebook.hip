@@ -24,6 +24,13 @@ __host__ __device__ inline uint32_t pow2ceil(uint32_t v)
     return p;
 }
 
+// The codebook and the decoder tables run as one workgroup per field of kCb
+// threads: the merge rounds are short and mostly a per-item binary search,
+// and the table entries are independent, so one item per thread keeps each
+// step to a few dependent LDS reads.
+constexpr uint32_t kCb = 1024;
+constexpr int kCbWaves = kCb / kWave;
+
 size_t codebook_lds_bytes(uint32_t n_bins)
 {
     const uint32_t P = max(pow2ceil(n_bins), 512u);
@@ -32,21 +39,22 @@ size_t codebook_lds_bytes(uint32_t n_bins)
 
 // Rank of every symbol among the symbols of equal length with a smaller index,
 // and per-length counts, using wave ballots.  Fills
-//   rank_out[k] for the symbols s = 64 * (w + 4k) + lane handled by this wave,
+//   rank_out[k] for the symbols s = 64 * (w + k NT / 64) + lane handled by wave w of NT threads,
 //   cnt[b * 65 + L] = symbols of length L in block b, then prefix over blocks.
 // len_s: LDS code lengths.  After return (block-synchronised):
 //   cnt[b*65+L] = number of symbols of length L in blocks < b,
 //   cntL[L]     = total symbols of length L.
+template <uint32_t NT>
 __device__ void canonical_rank(const uint8_t* len_s, uint32_t nb, uint16_t* cnt, uint32_t* cntL,
                                uint32_t rank_out[16])
 {
     const int l = lane_id();
     const int w = threadIdx.x / kWave;
     const uint32_t nblk = (nb + 63) / 64;
-    for (uint32_t i = threadIdx.x; i < nblk * 65; i += kBlock) cnt[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nblk * 65; i += NT) cnt[i] = 0;
     __syncthreads();
     int k = 0;
-    for (uint32_t b = w; b < nblk; b += kWavesPerBlock, ++k) {
+    for (uint32_t b = w; b < nblk; b += (NT / kWave), ++k) {
         const uint32_t s = b * 64 + l;
         const uint32_t L = s < nb ? len_s[s] : 0u;
         uint64_t todo = ballot(L != 0);
@@ -75,7 +83,7 @@ __device__ void canonical_rank(const uint8_t* len_s, uint32_t nb, uint16_t* cnt,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict__ F)
+__global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.x];
     EBC_G FieldDyn* dy = fd.dyn;
@@ -90,11 +98,11 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
     uint8_t* dep = (uint8_t*)iw;                        // R1 reuse: 2 Pa bytes
     uint8_t* len_s = dep + 2 * Pa;                      // R1 reuse: Pa bytes
     __shared__ uint32_t s_m;
-    __shared__ uint32_t s_red[kWavesPerBlock];
+    __shared__ uint32_t s_red[kCbWaves];
 
     // leaves: key = (freq << 16) | symbol; absent symbols sort last
     uint32_t used = 0;
-    for (uint32_t s = threadIdx.x; s < P; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < P; s += kCb) {
         const uint32_t h = s < nb ? fd.hist[s] : 0u;
         keys[s] = h ? (((uint64_t)h << 16) | s) : ~0ull;
         used += h != 0;
@@ -102,17 +110,48 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
     used = wave_sum_u32(used);
     if (lane_id() == 0) s_red[threadIdx.x / kWave] = used;
     __syncthreads();
-    if (threadIdx.x == 0) s_m = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int k = 0; k < kCbWaves; ++k) t += s_red[k];
+        s_m = t;
+    }
     // bitonic sort of P keys, ascending
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < P; i += kBlock) {
-                const uint32_t p = i ^ j;
-                if (p > i) {
-                    const uint64_t a = keys[i], b = keys[p];
-                    const bool up = (i & k) == 0;
-                    if ((a > b) == up) keys[i] = b, keys[p] = a;
+    if (P <= kCb) {
+        // one key per thread in a register: partners closer than a wave are
+        // exchanged by lane shuffles, farther ones through LDS
+        __syncthreads();
+        const uint32_t i = threadIdx.x;
+        uint64_t v = i < P ? keys[i] : ~0ull;
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                uint64_t u;
+                if (j < (uint32_t)kWave) {
+                    u = ((uint64_t)(uint32_t)__shfl_xor((int)(v >> 32), (int)j) << 32) |
+                        (uint32_t)__shfl_xor((int)(uint32_t)v, (int)j);
+                } else {
+                    __syncthreads();
+                    if (i < P) keys[i] = v;
+                    __syncthreads();
+                    u = i < P ? keys[i ^ j] : ~0ull;
+                }
+                // the lower index of an ascending pair keeps the minimum
+                const bool lower = (i & j) == 0, up = (i & k) == 0;
+                v = (lower == up) ? min(v, u) : max(v, u);
+            }
+        }
+        __syncthreads();
+        if (i < P) keys[i] = v;
+    } else {
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                for (uint32_t i = threadIdx.x; i < P; i += kCb) {
+                    const uint32_t p = i ^ j;
+                    if (p > i) {
+                        const uint64_t a = keys[i], b = keys[p];
+                        const bool up = (i & k) == 0;
+                        if ((a > b) == up) keys[i] = b, keys[p] = a;
+                    }
                 }
             }
         }
@@ -129,72 +168,72 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
     // any later one (ties: leaf before internal node, older internal node
     // before newer), so all of them can be paired in merged order at once;
     // an odd one out waits for the next round.  This reproduces the sequential
-    // two-queue picks exactly.
-    __shared__ uint32_t s_li, s_ih, s_ni, s_t;
-    if (threadIdx.x == 0) s_li = 0, s_ih = 0, s_ni = 0;
-    __syncthreads();
-    while (m > 1) {
-        const uint32_t li = s_li, ih = s_ih, ni = s_ni;
-        if (ni + 1 >= m) break;
-        if (threadIdx.x == 0) {
-            uint32_t a = li, b = ih, t = 0;
-            for (int k = 0; k < 2; ++k) {
-                const uint32_t lw = a < m ? (uint32_t)(keys[a] >> 16) : 0xFFFFFFFFu;
-                if (a < m && (b == ni || lw <= iw[b])) t += lw, ++a;
-                else t += iw[b], ++b;
+    // two-queue picks exactly.  The rounds run in one wave: ballots instead of
+    // workgroup barriers, and a wave's LDS accesses complete in order, so the
+    // new nodes are cleared and then summed with LDS atomics in place.
+    if (threadIdx.x < (uint32_t)kWave) {
+        const uint32_t lane = lane_id();
+        auto lw = [&](uint32_t i) { return (uint32_t)(keys[i] >> 16); };
+        uint32_t li = 0, ih = 0, ni = 0;
+        while (ni + 1 < m) {
+            // the two smallest available items, from the four queue heads
+            const uint32_t l0 = li < m ? lw(li) : 0xFFFFFFFFu, l1 = li + 1 < m ? lw(li + 1) : 0xFFFFFFFFu;
+            const uint32_t i0 = ih < ni ? iw[ih] : 0xFFFFFFFFu, i1 = ih + 1 < ni ? iw[ih + 1] : 0xFFFFFFFFu;
+            uint32_t t, a = li, b = ih;
+            {
+                const bool f0 = a < m && (b == ni || l0 <= i0);
+                t = f0 ? l0 : i0;
+                a += f0, b += !f0;
+                const uint32_t la = a == li ? l0 : l1, ib = b == ih ? i0 : i1;
+                const bool f1 = a < m && (b == ni || la <= ib);
+                t += f1 ? la : ib;
             }
-            s_t = t;
-        }
-        __syncthreads();
-        const uint32_t t = s_t;
-        // available leaves / internal nodes of weight <= t (both lists sorted)
-        uint32_t cl = 0, ci = 0;
-        for (uint32_t base = li;; base += kBlock) {
-            const uint32_t i = base + threadIdx.x;
-            const int c = __syncthreads_count(i < m && (uint32_t)(keys[i] >> 16) <= t);
-            cl += c;
-            if (c < kBlock) break;
-        }
-        for (uint32_t base = ih;; base += kBlock) {
-            const uint32_t j = base + threadIdx.x;
-            const int c = __syncthreads_count(j < ni && iw[j] <= t);
-            ci += c;
-            if (c < kBlock) break;
-        }
-        const uint32_t np = (cl + ci) / 2;
-        for (uint32_t k = threadIdx.x; k < np; k += kBlock) iw[ni + k] = 0;
-        __syncthreads();
-        // merged position of every item, then parent and weight of its pair
-        for (uint32_t i = threadIdx.x; i < cl; i += kBlock) {
-            const uint32_t wi = (uint32_t)(keys[li + i] >> 16);
-            uint32_t a = 0, b = ci;  // internal nodes lighter than the leaf
-            while (a < b) {
-                const uint32_t mid = (a + b) >> 1;
-                if (iw[ih + mid] < wi) a = mid + 1;
-                else b = mid;
+            // available leaves / internal nodes of weight <= t (prefixes of sorted lists)
+            uint32_t cl = 0, ci = 0;
+            for (uint32_t base = li;; base += kWave) {
+                const uint32_t i = base + lane;
+                const uint32_t c = (uint32_t)__popcll(ballot(i < m && lw(i) <= t));
+                cl += c;
+                if (c < (uint32_t)kWave) break;
             }
-            const uint32_t pos = i + a;
-            if (pos < 2 * np) {
-                parent[li + i] = (uint16_t)(m + ni + pos / 2);
-                atomicAdd(&iw[ni + pos / 2], wi);
+            for (uint32_t base = ih;; base += kWave) {
+                const uint32_t j = base + lane;
+                const uint32_t c = (uint32_t)__popcll(ballot(j < ni && iw[j] <= t));
+                ci += c;
+                if (c < (uint32_t)kWave) break;
             }
-        }
-        for (uint32_t j = threadIdx.x; j < ci; j += kBlock) {
-            const uint32_t wj = iw[ih + j];
-            uint32_t a = 0, b = cl;  // leaves not heavier than the node
-            while (a < b) {
-                const uint32_t mid = (a + b) >> 1;
-                if ((uint32_t)(keys[li + mid] >> 16) <= wj) a = mid + 1;
-                else b = mid;
+            const uint32_t np = (cl + ci) / 2;
+            for (uint32_t k = lane; k < np; k += kWave) iw[ni + k] = 0;
+            // merged position of every item: its parent, and its weight added
+            // to that parent's
+            for (uint32_t i = lane; i < cl; i += kWave) {
+                const uint32_t wi = lw(li + i);
+                uint32_t lo = 0, hi = ci;  // internal nodes lighter than the leaf
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (iw[ih + mid] < wi) lo = mid + 1;
+                    else hi = mid;
+                }
+                const uint32_t pos = i + lo;
+                if (pos < 2 * np) {
+                    parent[li + i] = (uint16_t)(m + ni + pos / 2);
+                    atomicAdd(&iw[ni + pos / 2], wi);
+                }
             }
-            const uint32_t pos = j + a;
-            if (pos < 2 * np) {
-                parent[m + ih + j] = (uint16_t)(m + ni + pos / 2);
-                atomicAdd(&iw[ni + pos / 2], wj);
+            for (uint32_t j = lane; j < ci; j += kWave) {
+                const uint32_t wj = iw[ih + j];
+                uint32_t lo = 0, hi = cl;  // leaves not heavier than the node
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (lw(li + mid) <= wj) lo = mid + 1;
+                    else hi = mid;
+                }
+                const uint32_t pos = j + lo;
+                if (pos < 2 * np) {
+                    parent[m + ih + j] = (uint16_t)(m + ni + pos / 2);
+                    atomicAdd(&iw[ni + pos / 2], wj);
+                }
             }
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
             uint32_t dl = cl, di = ci;
             if ((cl + ci) & 1) {
                 // the last item in merged order stays: an internal node comes
@@ -202,44 +241,53 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
                 bool last_is_leaf;
                 if (ci == 0) last_is_leaf = true;
                 else if (cl == 0) last_is_leaf = false;
-                else last_is_leaf = (uint32_t)(keys[li + cl - 1] >> 16) > iw[ih + ci - 1];
+                else last_is_leaf = lw(li + cl - 1) > iw[ih + ci - 1];
                 if (last_is_leaf) --dl;
                 else --di;
             }
-            s_li = li + dl, s_ih = ih + di, s_ni = ni + np;
+            li += dl, ih += di, ni += np;
         }
-        __syncthreads();
     }
+    __syncthreads();
     if (threadIdx.x == 0 && m > 1) parent[2 * m - 2] = (uint16_t)(2 * m - 2);  // the root points to itself
     __syncthreads();
     // depths by pointer jumping over nodes 0 .. 2m-2 (depth <= 64 < 2^7)
     const uint32_t nn = m > 1 ? 2 * m - 1 : 1;
     const uint32_t root = nn - 1;
-    for (uint32_t v = threadIdx.x; v < nn; v += kBlock) dep[v] = v == root ? 0 : 1;
+    for (uint32_t v = threadIdx.x; v < nn; v += kCb) dep[v] = v == root ? 0 : 1;
     if (m == 1 && threadIdx.x == 0) dep[0] = 1;  // a lone symbol gets one bit
     __syncthreads();
     if (m > 1) {
+        // at most kNodes nodes per thread (2 * 4096 - 1 nodes, kCb threads),
+        // in registers through fully unrolled loops
+        constexpr int kNodes = (2 * kMaxBins + kCb - 1) / kCb;
         for (int round = 0; round < 7; ++round) {
-            uint32_t nd[32], na[32];
-            int c = 0;
-            for (uint32_t v = threadIdx.x; v < nn; v += kBlock, ++c) {
-                const uint32_t a = parent[v];
-                nd[c] = dep[v] + (a == v ? 0u : dep[a]);
-                na[c] = parent[a];
+            uint32_t nd[kNodes], na[kNodes];
+#pragma unroll
+            for (int c = 0; c < kNodes; ++c) {
+                const uint32_t v = threadIdx.x + c * kCb;
+                if (v < nn) {
+                    const uint32_t a = parent[v];
+                    nd[c] = dep[v] + (a == v ? 0u : dep[a]);
+                    na[c] = parent[a];
+                }
             }
             __syncthreads();
-            c = 0;
-            for (uint32_t v = threadIdx.x; v < nn; v += kBlock, ++c) {
-                dep[v] = (uint8_t)min(nd[c], 255u);
-                parent[v] = (uint16_t)na[c];
+#pragma unroll
+            for (int c = 0; c < kNodes; ++c) {
+                const uint32_t v = threadIdx.x + c * kCb;
+                if (v < nn) {
+                    dep[v] = (uint8_t)min(nd[c], 255u);
+                    parent[v] = (uint16_t)na[c];
+                }
             }
             __syncthreads();
         }
     }
     // leaf lengths -> symbols
-    for (uint32_t s = threadIdx.x; s < Pa; s += kBlock) len_s[s] = 0;
+    for (uint32_t s = threadIdx.x; s < Pa; s += kCb) len_s[s] = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < m; i += kBlock) len_s[keys[i] & 0xFFFFu] = dep[i];
+    for (uint32_t i = threadIdx.x; i < m; i += kCb) len_s[keys[i] & 0xFFFFu] = dep[i];
     __syncthreads();
 
     // canonical codes (R0 reused for the per-block counts)
@@ -247,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
     uint32_t* cntL = (uint32_t*)(((uintptr_t)(cnt + ((nb + 63) / 64) * 65 + 2) + 7) & ~(uintptr_t)7);
     uint64_t* first = (uint64_t*)(((uintptr_t)(cntL + 65) + 7) & ~(uintptr_t)7);
     uint32_t rank[16];
-    canonical_rank(len_s, nb, cnt, cntL, rank);
+    canonical_rank<kCb>(len_s, nb, cnt, cntL, rank);
     if (threadIdx.x == 0) {
         uint64_t c = 0;
         uint32_t maxl = 0;
@@ -264,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
     const int w = threadIdx.x / kWave;
     uint64_t bits = 0;
     int k = 0;
-    for (uint32_t b = w; b < (nb + 63) / 64; b += kWavesPerBlock, ++k) {
+    for (uint32_t b = w; b < (nb + 63) / 64; b += kCbWaves, ++k) {
         const uint32_t s = b * 64 + l;
         if (s < nb) {
             const uint32_t L = len_s[s];
@@ -279,11 +327,12 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
         }
     }
     bits = wave_sum_u64(bits);
-    __shared__ uint64_t s_bits[kWavesPerBlock];
+    __shared__ uint64_t s_bits[kCbWaves];
     if (l == 0) s_bits[w] = bits;
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint64_t tb = s_bits[0] + s_bits[1] + s_bits[2] + s_bits[3];
+        uint64_t tb = 0;
+        for (int k = 0; k < kCbWaves; ++k) tb += s_bits[k];
         dy->huff_bits = tb;
         int codec;
         if (fd.codec_req == REQ_AUTO) codec = 100ull * tb <= 109ull * fd.n ? ARC_RLE : ARC_HUFFMAN;
@@ -300,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_codebook(const FieldDesc* __restrict
 
 
 
-__global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__ F,
+__global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
                                                    uint8_t* __restrict__ tabs)
 {
     const FieldDesc& fd = F[blockIdx.x];
@@ -318,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
     const uint8_t* alen = fd.arc + kHdr;
-    for (uint32_t s = threadIdx.x; s < nb; s += kBlock) {
+    for (uint32_t s = threadIdx.x; s < nb; s += kCb) {
         const uint8_t L = alen[s];
         if (L > kMaxDecodeLen) s_bad = 1;
         len_s[s] = L;
@@ -329,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         return;
     }
     uint32_t rank[16];
-    canonical_rank(len_s, nb, cnt, cntL, rank);
+    canonical_rank<kCb>(len_s, nb, cnt, cntL, rank);
     if (threadIdx.x == 0) {
         // canonical first codes; the lengths must satisfy Kraft's inequality
         // (first[L] + count[L] <= 2^L at every length), otherwise the archive
@@ -360,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     const int l = lane_id();
     const int w = threadIdx.x / kWave;
     int k = 0;
-    for (uint32_t b = w; b < (nb + 63) / 64; b += kWavesPerBlock, ++k) {
+    for (uint32_t b = w; b < (nb + 63) / 64; b += kCbWaves, ++k) {
         const uint32_t s = b * 64 + l;
         if (s < nb) {
             const uint32_t L = len_s[s];
@@ -368,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nb; i += kBlock) T->perm[i] = perm_s[i];
+    for (uint32_t i = threadIdx.x; i < nb; i += kCb) T->perm[i] = perm_s[i];
     // left-aligned ends of the code space of lengths <= L (monotone in L)
     __syncthreads();
     if (threadIdx.x <= 64) {
@@ -385,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     // zero) still decodes a codeword of length <= r correctly, because such a
     // codeword depends on its own bits only.
     __shared__ uint32_t t1[1u << kLutBits];
-    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kBlock) {
+    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
         uint32_t e = 0;
         for (uint32_t l = 1; l <= (uint32_t)kLutBits; ++l) {
             const uint64_t v = p >> (kLutBits - l);
@@ -401,8 +450,8 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
     // each a block of 2^k entries resolving the next k bits.
     __shared__ uint16_t lslot[1u << kLutBits];
     __shared__ uint16_t lpref[1u << kLutBits];
-    __shared__ uint32_t s_wsum[kWavesPerBlock];
-    constexpr uint32_t kPer = (1u << kLutBits) / kBlock;
+    __shared__ uint32_t s_wsum[kCbWaves];
+    constexpr uint32_t kPer = (1u << kLutBits) / kCb;
     {
         uint32_t c = 0;
         for (uint32_t i = 0; i < kPer; ++i) c += t1[threadIdx.x * kPer + i] == 0;
@@ -423,7 +472,8 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         }
     }
     __syncthreads();
-    const uint32_t nlong = s_wsum[0] + s_wsum[1] + s_wsum[2] + s_wsum[3];
+    uint32_t nlong = 0;
+    for (int v = 0; v < kCbWaves; ++v) nlong += s_wsum[v];
     const uint32_t maxl = s_maxl;
     uint32_t l2k = 0;
     if (maxl > (uint32_t)kLutBits && nlong > 0) {
@@ -431,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         while (l2k > 0 && (nlong << l2k) > kL2Size) --l2k;
     }
     const uint32_t l2n = l2k ? nlong << l2k : 0u;
-    for (uint32_t i = threadIdx.x; i < l2n; i += kBlock) {
+    for (uint32_t i = threadIdx.x; i < l2n; i += kCb) {
         const uint32_t p = lpref[i >> l2k];
         const uint64_t wv = ((uint64_t)p << l2k) | (i & ((1u << l2k) - 1));  // kLutBits + l2k bits
         uint32_t e = 0;
@@ -445,7 +495,7 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
         T->l2[i] = e;
     }
     if (threadIdx.x == 0) T->l2k = l2k, T->l2n = l2n;
-    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kBlock) {
+    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
         uint64_t e = 0;
         uint32_t pos = 0, n = 0;
         while (n < 3 && pos < (uint32_t)kLutBits) {
@@ -466,13 +516,13 @@ __global__ __launch_bounds__(kBlock) void k_dectab(const FieldDesc* __restrict__
 
 hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kBlock), codebook_lds_bytes(n_bins), s, F);
+    hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kCb), codebook_lds_bytes(n_bins), s, F);
     return hipGetLastError();
 }
 
 hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dectab, dim3(nf), dim3(kBlock), 0, s, F, tabs);
+    hipLaunchKernelGGL(k_dectab, dim3(nf), dim3(kCb), 0, s, F, tabs);
     return hipGetLastError();
 }
 

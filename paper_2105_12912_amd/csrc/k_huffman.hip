@@ -203,10 +203,15 @@ struct WriteProc {
         const auto* dy = kconst(fd.dyn);
         const uint32_t nb = fd.n_bins, hc = fd.hc;
         uint64_t* code_s = lds64;
+        // Each wave packs its chunk in a word buffer of its own, and a wave's
+        // LDS accesses complete in order, so clearing, packing and copying
+        // out need no barrier; only a new field's code table (shared by the
+        // workgroup, whose waves all work on one field) does.
         uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
-        __syncthreads();  // previous chunk's words are out of the buffers
         if (u.f != cur) {
+            __syncthreads();
             for (uint32_t s = threadIdx.x; s < nb; s += kWave * huff_cpw(64 * S)) code_s[s] = fd.code[s];
+            __syncthreads();
             cur = u.f;
         }
         const bool live = u.c < fd.n_hch;
@@ -214,7 +219,6 @@ struct WriteProc {
         uint32_t mid = 0;
         const uint32_t nw = (cbits + 31) / 32;
         for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
-        __syncthreads();
         if (live) {
             const uint64_t lo = (uint64_t)u.c * hc + (uint64_t)lane_id() * S;
             uint32_t mybits = 0;
@@ -239,7 +243,6 @@ struct WriteProc {
             }
             if (nacc) atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
         }
-        __syncthreads();
         if (live) {
             EBC_G uint8_t* arc = fd.arc;
             const auto* wk = (const __attribute__((address_space(4))) uint32_t*)woff;

@@ -72,19 +72,32 @@ __device__ __forceinline__ uint32_t block_excl_scan_rle(uint32_t v, uint32_t* to
 }
 
 // Both encode passes are persistent (grid stride over the tiles).
+// Grid-stride step past field fd's RLE tiles (those of a field that is not
+// run-length coded): the first tile index of this workgroup's stride at or
+// beyond the field's end, so such a field costs one iteration per workgroup.
+__device__ __forceinline__ uint32_t skip_field(const FieldDesc& fd, uint32_t t)
+{
+    const uint32_t end = fd.rt_base + fd.n_rt;
+    return t + ((end - t + gridDim.x - 1) / gridDim.x) * gridDim.x;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restrict__ F, int nf,
                                                       uint32_t* __restrict__ rcnt, uint32_t units)
 {
-    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+    for (uint32_t t = blockIdx.x; t < units;) {
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
         const EBC_G FieldDyn* dy = fd.dyn;
-        if (dy->status != ST_OK || dy->codec != ARC_RLE) continue;
+        if (dy->status != ST_OK || dy->codec != ARC_RLE) {
+            t = skip_field(fd, t);
+            continue;
+        }
         uint16_t c[kRleItems];
         const uint32_t flags = run_flags(fd, (uint64_t)(t - fd.rt_base) * kRleTile, c);
         uint32_t tot;
         block_excl_scan_rle(__popc(flags), &tot);
         if (threadIdx.x == 0) rcnt[t] = tot;
+        t += gridDim.x;
     }
 }
 
@@ -95,7 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
         const EBC_G FieldDyn* dy = fd.dyn;
-        if (dy->status != ST_OK || dy->codec != ARC_RLE) continue;
+        if (dy->status != ST_OK || dy->codec != ARC_RLE) {
+            t = skip_field(fd, t) - gridDim.x;  // the loop step adds it back
+            continue;
+        }
         const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
         uint16_t c[kRleItems];
         const uint32_t flags = run_flags(fd, lo, c);

@@ -23,6 +23,11 @@ __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 // native vector types for streaming (non-temporal) loads and stores
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// the same vectors at dword alignment: multi-dword global accesses need only
+// 4-byte alignment, so rows that are not 16-byte aligned still move a quad in
+// one access
+typedef f32x4 f32x4_a4 __attribute__((aligned(4)));
+typedef u32x2 u32x2_a4 __attribute__((aligned(4)));
 __device__ __forceinline__ f32x4 ld_nt_f4(const EBC_G float* p)
 {
     return __builtin_nontemporal_load((const EBC_G f32x4*)p);

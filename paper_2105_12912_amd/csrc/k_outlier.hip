@@ -62,6 +62,28 @@ __global__ __launch_bounds__(kBlock) void k_outlier_write(const FieldDesc* __res
     // 8 codes at a time where aligned
     for (; i < b && (i & 7); ++i)
         if (q[i] == 0 && pos < end) oidx[pos] = (uint32_t)i, oval[pos] = fd.dsc[i], ++pos;
+    // 32 codes at a time with their deltas loaded alongside (the deltas of
+    // non-outliers are never used), so a block costs one memory round trip
+    // however many outliers it holds
+    for (; i + 32 <= b && pos < end; i += 32) {
+        uint4 cv[4], dv[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) cv[k] = *(const EBC_G uint4*)(q + i + 8 * k);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dv[k] = *(const EBC_G uint4*)(fd.dsc + i + 4 * k);
+#pragma unroll
+        for (int e = 0; e < 32; ++e) {
+            const uint4& c4 = cv[e / 8];
+            const uint32_t cw = (e / 2) % 4 == 0 ? c4.x : (e / 2) % 4 == 1 ? c4.y : (e / 2) % 4 == 2 ? c4.z : c4.w;
+            const uint4& d4 = dv[e / 4];
+            const uint32_t dw = e % 4 == 0 ? d4.x : e % 4 == 1 ? d4.y : e % 4 == 2 ? d4.z : d4.w;
+            if (((cw >> (16 * (e & 1))) & 0xFFFFu) == 0 && pos < end) {
+                oidx[pos] = (uint32_t)(i + e);
+                oval[pos] = (int32_t)dw;
+                ++pos;
+            }
+        }
+    }
     for (; i + 8 <= b && pos < end; i += 8) {
         const uint4 v = *(const EBC_G uint4*)(q + i);
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};

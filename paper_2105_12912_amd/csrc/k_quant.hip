@@ -176,6 +176,9 @@ __device__ __forceinline__ void load_quad(const EBC_G float* __restrict__ p, uin
         } else {
             v[0] = v[1] = v[2] = v[3] = 0.f;
         }
+    } else if (nvalid == 4) {
+        const f32x4 t = *(const EBC_G f32x4_a4*)(p + i);
+        v[0] = t.x, v[1] = t.y, v[2] = t.z, v[3] = t.w;
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k) v[k] = k < nvalid ? p[i + k] : 0.f;
@@ -193,6 +196,10 @@ __device__ __forceinline__ void store_codes(EBC_G uint16_t* __restrict__ q, uint
             t.y = c[2] | (c[3] << 16);
             *(EBC_G uint2*)(q + i) = t;
         }
+    } else if (nvalid == 4 && (i & 1) == 0) {
+        // four codes at an even index: one dword-aligned 8-byte store
+        const u32x2 t = {c[0] | (c[1] << 16), c[2] | (c[3] << 16)};
+        *(EBC_G u32x2_a4*)(q + i) = t;
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)

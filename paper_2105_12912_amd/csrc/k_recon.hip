@@ -26,6 +26,7 @@ template <bool VEC>
 __device__ __forceinline__ u32x2 load_packed(const EBC_G uint16_t* __restrict__ q, uint64_t i, int nvalid)
 {
     if (VEC && nvalid == 4) return ld_nt_u2(q + i);
+    if (nvalid == 4 && (i & 1) == 0) return *(const EBC_G u32x2_a4*)(q + i);  // dword-aligned
     uint32_t c[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] = k < nvalid ? q[i + k] : 1u;
@@ -46,6 +47,8 @@ __device__ __forceinline__ void store_quad(EBC_G float* __restrict__ o, uint64_t
 {
     if (VEC && nvalid == 4) {
         st_nt_f4(o + i, f32x4{v[0], v[1], v[2], v[3]});
+    } else if (nvalid == 4) {
+        *(EBC_G f32x4_a4*)(o + i) = f32x4{v[0], v[1], v[2], v[3]};  // dword-aligned
     } else {
 #pragma unroll
         for (int k = 0; k < 4; ++k)

@@ -430,7 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
         const FieldDesc& fd = F[f];
-        const EBC_G FieldDyn* dy = fd.dyn;
+        const auto* dy = kconst(fd.dyn);  // scalar loads: no wait on the previous tile's stores
         if (dy->status != ST_OK || dy->codec == ARC_CONST) continue;  // uniform over the workgroup
         if (f != cur) {
             if (cur >= 0) flush_hist(F[cur], qc, sh_hist);
@@ -472,7 +472,8 @@ constexpr int kHistSplit = 64;
 __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.z];
-    if (fd.dyn->status != ST_OK || fd.dyn->codec == ARC_CONST) return;
+    const auto* dy = kconst(fd.dyn);
+    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const uint32_t b = blockIdx.x * kBlock + threadIdx.x;
     if (b >= fd.n_bins) return;
     const uint32_t nb = fd.n_bins;

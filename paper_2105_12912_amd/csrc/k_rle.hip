@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restric
     for (uint32_t t = blockIdx.x; t < units;) {
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
-        const EBC_G FieldDyn* dy = fd.dyn;
+        const auto* dy = kconst(fd.dyn);
         if (dy->status != ST_OK || dy->codec != ARC_RLE) {
             t = skip_field(fd, t);
             continue;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
     for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
-        const EBC_G FieldDyn* dy = fd.dyn;
+        const auto* dy = kconst(fd.dyn);
         if (dy->status != ST_OK || dy->codec != ARC_RLE) {
             t = skip_field(fd, t) - gridDim.x;  // the loop step adds it back
             continue;
@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
 __global__ __launch_bounds__(kBlock) void k_rle_len(const FieldDesc* __restrict__ F)
 {
     const FieldDesc& fd = F[blockIdx.y];
-    const EBC_G FieldDyn* dy = fd.dyn;
+    const auto* dy = kconst(fd.dyn);
     if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
     const uint64_t R = dy->n_runs;
     EBC_G uint32_t* len = (EBC_G uint32_t*)(fd.arc + dy->off_rlen);

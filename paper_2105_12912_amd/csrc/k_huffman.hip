@@ -190,12 +190,40 @@ __device__ __forceinline__ void put_bits(uint64_t& acc, uint32_t& nacc, uint32_t
     }
 }
 
+// The writer's LDS copy of the codebook: a codeword of at most 32 bits sits
+// left-aligned in the high word with its length in the low byte, so that
+// appending it is one shift and one OR; a longer codeword keeps only its
+// length here and is read from the codebook itself.
+__device__ __forceinline__ uint64_t write_entry(uint64_t packed)
+{
+    const uint32_t L = (uint32_t)(packed >> 56);
+    if (L == 0 || L > 32) return L;
+    return ((uint64_t)((uint32_t)packed << (32 - L)) << 32) | L;
+}
+
+// append a codeword of L <= 32 bits given left-aligned in cw
+__device__ __forceinline__ void put_left(uint64_t& acc, uint32_t& nacc, uint32_t& w, uint32_t* wbuf,
+                                         uint32_t cw, uint32_t L)
+{
+    acc |= (uint64_t)cw << (32 - nacc);
+    nacc += L;
+    if (nacc >= 32) {
+        atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
+        ++w;
+        acc <<= 32;
+        nacc -= 32;
+    }
+}
+
 template <uint32_t S>
 struct WriteProc {
     const FieldDesc* F;
     const uint32_t* woff;
     uint64_t* lds64;
     int cur;
+    // up to 16 symbols per lane keep their table entries in registers between
+    // the bit count and the packing; wider lanes look them up twice
+    static constexpr bool kKeep = S <= 16;
     __device__ __forceinline__ void operator()(const EncUnit& u, const SymRaw<S>& r)
     {
         if (!u.ok) return;
@@ -210,36 +238,56 @@ struct WriteProc {
         uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
         if (u.f != cur) {
             __syncthreads();
-            for (uint32_t s = threadIdx.x; s < nb; s += kWave * huff_cpw(64 * S)) code_s[s] = fd.code[s];
+            for (uint32_t s = threadIdx.x; s < nb; s += kWave * huff_cpw(64 * S))
+                code_s[s] = write_entry(fd.code[s]);
             __syncthreads();
             cur = u.f;
         }
         const bool live = u.c < fd.n_hch;
         const uint32_t cbits = live ? kconst(fd.hbits)[u.c] : 0u;
-        uint32_t mid = 0;
         const uint32_t nw = (cbits + 31) / 32;
-        for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
-        if (live) {
-            const uint64_t lo = (uint64_t)u.c * hc + (uint64_t)lane_id() * S;
-            uint32_t mybits = 0;
+        const uint64_t lo = (uint64_t)u.c * hc + (uint64_t)lane_id() * S;
+        // symbols past the field's end take the empty entry
+        const uint32_t m = live && lo < fd.n ? (uint32_t)min<uint64_t>(S, fd.n - lo) : 0u;
+        uint64_t e[kKeep ? S : 1];
+        uint32_t mybits = 0, lmax = 0;
 #pragma unroll
-            for (uint32_t k = 0; k < S; ++k)
-                if (lo + k < fd.n) mybits += (uint32_t)(code_s[r.at(k)] >> 56);
+        for (uint32_t k = 0; k < S; ++k) {
+            const uint64_t v0 = code_s[k < m ? r.at(k) : 0u];
+            const uint64_t v = k < m ? v0 : 0ull;
+            if (kKeep) e[kKeep ? k : 0] = v;
+            const uint32_t L = (uint32_t)v & 0xFFu;
+            mybits += L;
+            lmax = max(lmax, L);
+        }
+        for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
+        uint32_t mid = 0;
+        if (live) {
             const uint32_t b0 = wave_incl_scan_u32(mybits) - mybits;
             // lane 32 starts at symbol hc/2: the chunk's midpoint bit offset
             // (its bit count when the chunk is shorter)
             mid = (uint32_t)__shfl((int)b0, 32);
             uint32_t w = b0 >> 5, nacc = b0 & 31;
             uint64_t acc = 0;
+            if (!__any(lmax > 32)) {
 #pragma unroll
-            for (uint32_t k = 0; k < S; ++k) {
-                if (lo + k >= fd.n) continue;
-                const uint64_t e = code_s[r.at(k)];
-                const uint32_t L = (uint32_t)(e >> 56);
-                const uint64_t cw = e & ((1ull << 56) - 1);
-                if (L > 32) put_bits(acc, nacc, w, wbuf, cw >> 32, L - 32);  // rare long code
-                const uint32_t low = L > 32 ? 32u : L;
-                put_bits(acc, nacc, w, wbuf, cw & (low == 32 ? 0xFFFFFFFFull : ((1ull << low) - 1)), low);
+                for (uint32_t k = 0; k < S; ++k) {
+                    const uint64_t v = kKeep ? e[kKeep ? k : 0] : (k < m ? code_s[r.at(k)] : 0ull);
+                    put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), (uint32_t)v & 0xFFu);
+                }
+            } else {  // a codeword longer than 32 bits somewhere in the chunk
+#pragma unroll
+                for (uint32_t k = 0; k < S; ++k) {
+                    const uint64_t v = k < m ? code_s[r.at(k)] : 0ull;
+                    const uint32_t L = (uint32_t)v & 0xFFu;
+                    if (L <= 32) {
+                        put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), L);
+                    } else {
+                        const uint64_t cw = fd.code[r.at(k)] & ((1ull << 56) - 1);
+                        put_bits(acc, nacc, w, wbuf, cw >> 32, L - 32);
+                        put_bits(acc, nacc, w, wbuf, cw & 0xFFFFFFFFull, 32);
+                    }
+                }
             }
             if (nacc) atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
         }

@@ -111,6 +111,47 @@ def test_huffman_chunk_sizes(E, hc):
     np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
 
 
+def fibonacci_deltas_field(m, seed):
+    """1D field whose quant-codes are m symbols with Fibonacci frequencies in a
+    seeded random order at abs eb = 0.5: the integers d whose first
+    differences within each 256-element chunk (the first element of a chunk
+    taken against zero) are those symbols, times the quantisation step (each
+    product is exact in fp32, so prequantisation returns d)."""
+    f = [1, 1]
+    while len(f) < m:
+        f.append(f[-1] + f[-2])
+    delta = np.repeat(np.arange(m, dtype=np.int64) - m // 2, f)
+    np.random.default_rng(seed).shuffle(delta)
+    c = np.cumsum(delta)
+    starts = np.arange(0, delta.size, 256)
+    base = np.concatenate([[0], c[starts[1:] - 1]])
+    d = c - np.repeat(base, np.diff(np.append(starts, delta.size)))
+    step = O.quant_step(float(np.abs(d).max()), 0.5)[0]
+    x = (d * step).astype(np.float32)
+    assert (x.astype(np.float64) == d * step).all()
+    assert O.quant_step(float(np.abs(x).max()), 0.5)[0] == step
+    return x, delta
+
+
+def test_codewords_longer_than_32_bits(E):
+    """A Fibonacci histogram over 34 symbols gives codewords of up to 33 bits:
+    the encoder's and the decoder's paths for codewords that span two words,
+    bit-exact against the oracle, at the default and the largest chunk size."""
+    x, delta = fibonacci_deltas_field(34, 31)
+    it = O.intermediates(x, 0.5, "abs")
+    np.testing.assert_array_equal(it["q"].astype(np.int64), delta + it["hist"].size // 2)
+    assert int(it["len"].max()) == 33
+    xd = dev(x)
+    for hc in (1024, 4096):
+        print(f"[long codes] hc={hc}", flush=True)
+        ref = O.compress(x, 0.5, "abs", codec="huffman", hc=hc)
+        a = E.compress(xd, 0.5, "abs", codec="huffman", huff_chunk=hc)
+        assert a.cpu().numpy().tobytes() == ref
+        y = E.decompress(a).cpu().numpy()
+        np.testing.assert_array_equal(y, x)
+        np.testing.assert_array_equal(bits(y), bits(O.decompress(ref)))
+
+
 def test_constant_field(E):
     x = np.full((33, 45), -2.5, np.float32)
     a = E.compress(dev(x), 1e-4)

@@ -241,3 +241,20 @@ def test_histogram_counts():
     h = O.histogram(q, 1024)
     assert h.sum() == q.size
     np.testing.assert_array_equal(h, np.bincount(q, minlength=1024))
+
+
+def test_fibonacci_weights_give_the_deepest_tree():
+    """Fibonacci weights F1..Fm make every merge take the previous subtree and
+    the next leaf, so the lengths are 1, 2, ..., m-2, m-1, m-1 (closed form);
+    m = 34 reaches 33-bit codewords, past one 32-bit word."""
+    m = 34
+    f = [1, 1]
+    while len(f) < m:
+        f.append(f[-1] + f[-2])
+    h = np.zeros(1024, dtype=np.uint64)
+    h[100:100 + m] = f
+    L = O.huffman_lengths(h)
+    got = sorted(int(v) for v in L[100:100 + m])
+    assert got == list(range(1, m - 1)) + [m - 1, m - 1]
+    assert int(L[100 + m - 1]) == 1 and int(L[100]) == m - 1 and int(L[101]) == m - 1
+    assert (L[:100] == 0).all() and (L[100 + m:] == 0).all()

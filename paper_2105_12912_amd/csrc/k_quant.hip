@@ -104,6 +104,8 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
     EBC_G FieldDyn* dy = fd.dyn;
     for (uint32_t b = threadIdx.x; b < fd.n_bins; b += kBlock) fd.hist[b] = 0;
     uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, bad = 0u;
+    // several partials in flight per wait
+#pragma unroll 8
     for (uint32_t u = threadIdx.x; u < fd.range_units; u += kBlock) {
         const EBC_G uint32_t* rp = fd.rpart + 3ull * u;
         kmin = min(kmin, rp[0]);
@@ -478,6 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restr
     if (b >= fd.n_bins) return;
     const uint32_t nb = fd.n_bins;
     uint32_t s = 0;
+#pragma unroll 8
     for (uint32_t r = blockIdx.y; r < fd.hrows; r += kHistSplit) s += fd.hpart[(uint64_t)r * nb + b];
     if (s) atomicAdd(&fd.hist[b], s);
 }

@@ -1,4 +1,7 @@
 // k_scan.hip -- exclusive prefix sum of a uint32 array (reduce-then-scan).
+// A first kernel writes every tile's sum; in the second, each workgroup adds
+// up the sums of the tiles before its own (a few loads per thread for the
+// tile counts used here) and scans its tile from there.
 //
 // Used for every offset computation of the path: ordered outlier positions
 // (per-segment counts), Huffman word offsets (per-chunk word counts), RLE run
@@ -68,33 +71,29 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     }
 }
 
-// single block: exclusive scan of the block sums, total in sums[nb]
-__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ sums, uint32_t nb)
+// total of an empty array
+__global__ void k_scan_empty(uint32_t* __restrict__ a) { a[0] = 0; }
+
+// sum of one value per thread over the block
+__device__ __forceinline__ uint32_t block_sum(uint32_t v)
 {
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += kScanTile) {
-        uint32_t v[kScanItems];
-        load_items(sums, nb, base, v);
-        uint32_t loc = 0;
+    __shared__ uint32_t s_r[kWavesPerBlock];
+    v = wave_sum_u32(v);
+    if (lane_id() == 0) s_r[threadIdx.x / kWave] = v;
+    __syncthreads();
+    uint32_t t = 0;
 #pragma unroll
-        for (int k = 0; k < kScanItems; ++k) loc += v[k];
-        uint32_t tot;
-        uint32_t off = block_excl_scan(loc, &tot) + carry;
-        const uint32_t i0 = base + threadIdx.x * kScanItems;
-#pragma unroll
-        for (int k = 0; k < kScanItems; ++k) {
-            if (i0 + k < nb) sums[i0 + k] = off;
-            off += v[k];
-        }
-        carry += tot;
-    }
-    if (threadIdx.x == 0) sums[nb] = carry;
+    for (int k = 0; k < kWavesPerBlock; ++k) t += s_r[k];
+    return t;
 }
 
 __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, uint32_t n,
                                                       const uint32_t* __restrict__ sums,
                                                       uint32_t nb)
 {
+    uint32_t pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) pre += sums[b];
+    pre = block_sum(pre);
     uint32_t v[kScanItems];
     const uint32_t base = blockIdx.x * kScanTile;
     load_items(a, n, base, v);
@@ -102,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) loc += v[k];
     uint32_t tot;
-    uint32_t off = block_excl_scan(loc, &tot) + sums[blockIdx.x];
+    uint32_t off = block_excl_scan(loc, &tot) + pre;
     const uint32_t i0 = base + threadIdx.x * kScanItems;
     if (i0 + kScanItems <= n) {
 #pragma unroll
@@ -121,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
             off += v[k];
         }
     }
-    if (blockIdx.x == nb - 1 && threadIdx.x == 0) a[n] = sums[nb];
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) a[n] = pre + tot;
 }
 
 uint32_t scan_tmp_words(uint32_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
@@ -129,13 +128,11 @@ uint32_t scan_tmp_words(uint32_t n) { return (n + kScanTile - 1) / kScanTile + 1
 hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s)
 {
     if (n == 0) {
-        // total of an empty array: write 0 with a one-thread kernel
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, a, 0u);
+        hipLaunchKernelGGL(k_scan_empty, dim3(1), dim3(1), 0, s, a);
         return hipGetLastError();
     }
     const uint32_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, a, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);
     hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s, a, n, tmp, nb);
     return hipGetLastError();
 }

@@ -60,7 +60,7 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
 {
     const int f = blockIdx.x;
     const FieldDesc& fd = F[f];
-    const EBC_G FieldDyn* dy = fd.dyn;
+    const auto* dy = kconst(fd.dyn);
     if (dy->status != ST_OK) return;
     EBC_G uint8_t* a = fd.arc;
     const int l = threadIdx.x;
@@ -103,6 +103,7 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
     if (dy->codec == ARC_CONST) return;
     const uint64_t no = dy->n_out;
     if (dy->codec == ARC_HUFFMAN) {
+#pragma unroll 8
         for (uint32_t s = l; s < fd.n_bins; s += kWave) a[kHdr + s] = fd.len[s];
         zero_gap(a, kHdr + fd.n_bins, dy->off_bits, l);
         zero_gap(a, dy->off_bits + 4ull * fd.n_hch, dy->off_words, l);

@@ -154,10 +154,15 @@ struct BitsProc {
         }
         if (u.c >= fd.n_hch) return;
         const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)lane_id() * S;
+        // symbols past the field's end count zero bits; every lookup is
+        // issued before any is used
+        const uint32_t m = lo < fd.n ? (uint32_t)min<uint64_t>(S, fd.n - lo) : 0u;
         uint32_t bits = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < S; ++k)
-            if (lo + k < fd.n) bits += len_s[r.at(k)];
+        for (uint32_t k = 0; k < S; ++k) {
+            const uint32_t L = len_s[k < m ? r.at(k) : 0u];
+            bits += k < m ? L : 0u;
+        }
         bits = wave_sum_u32(bits);
         if (lane_id() == 0) {
             fd.hbits[u.c] = bits;

@@ -102,7 +102,7 @@ def test_forced_codecs(E, codec, shape):
     np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
 
 
-@pytest.mark.parametrize("hc", [64, 256, 2048, 4096])
+@pytest.mark.parametrize("hc", [64, 128, 256, 512, 2048, 4096])
 def test_huffman_chunk_sizes(E, hc):
     x = rng_field((70, 90), 14, "noise")
     ref = O.compress(x, 1e-4, codec="huffman", hc=hc)
@@ -136,13 +136,13 @@ def fibonacci_deltas_field(m, seed):
 def test_codewords_longer_than_32_bits(E):
     """A Fibonacci histogram over 34 symbols gives codewords of up to 33 bits:
     the encoder's and the decoder's paths for codewords that span two words,
-    bit-exact against the oracle, at the default and the largest chunk size."""
+    bit-exact against the oracle, from the smallest to the largest chunk size."""
     x, delta = fibonacci_deltas_field(34, 31)
     it = O.intermediates(x, 0.5, "abs")
     np.testing.assert_array_equal(it["q"].astype(np.int64), delta + it["hist"].size // 2)
     assert int(it["len"].max()) == 33
     xd = dev(x)
-    for hc in (1024, 4096):
+    for hc in (64, 512, 1024, 4096):
         print(f"[long codes] hc={hc}", flush=True)
         ref = O.compress(x, 0.5, "abs", codec="huffman", hc=hc)
         a = E.compress(xd, 0.5, "abs", codec="huffman", huff_chunk=hc)

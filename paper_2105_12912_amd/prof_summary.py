@@ -10,11 +10,15 @@ Two inputs are understood:
   from counter units (KiB) to bytes: ``factor = copy_bytes / counter_bytes``.
   Per-kernel HBM bytes per dispatch are then ``(FETCH + WRITE) * factor``.
 
+A third form averages any other counters per dispatch (``--pmc`` passes of
+up to eight SQ counters each), for a list of kernels.
+
 Usage::
 
   python -m paper_2105_12912_amd.prof_summary stats DIR
   python -m paper_2105_12912_amd.prof_summary traffic --fetch DIR --write DIR \\
       --copy-fetch DIR --copy-write DIR --copy-bytes N [--json OUT --key WORKLOAD]
+  python -m paper_2105_12912_amd.prof_summary counters DIR [DIR ...] --kernels K1,K2,...
 """
 from __future__ import annotations
 
@@ -139,6 +143,28 @@ def cmd_traffic(a):
             f.write("\n")
 
 
+def counter_names(d: str):
+    with open(_find(d, "counter_collection.csv")) as f:
+        return sorted({r["Counter_Name"] for r in csv.DictReader(f)})
+
+
+def cmd_counters(a):
+    kernels = [k for k in a.kernels.split(",") if k]
+    table = defaultdict(dict)
+    for d in a.dirs:
+        for c in counter_names(d):
+            per = counter_per_dispatch(d, c)
+            for k in kernels:
+                if per.get(k):
+                    table[k][c] = (_avg(per[k]), len(per[k]))
+    for k in kernels:
+        if not table[k]:
+            continue
+        print(k)
+        for c, (v, n) in sorted(table[k].items()):
+            print(f"  {c:28s} {v:18.0f}   ({n} dispatches)")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -152,8 +178,11 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--json")
     t.add_argument("--key", default="nyx512")
+    c = sub.add_parser("counters")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kernels", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

@@ -299,10 +299,18 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
     if (threadIdx.x == 0) {
         uint64_t c = 0;
         uint32_t maxl = 0;
-        for (int L = 1; L <= 64; ++L) {
-            first[L] = c;
-            c = (c + cntL[L]) << 1;
-            if (cntL[L]) maxl = L;
+        // counts read 16 at a time so that the chain below waits on LDS
+        // four times, not 64
+        for (int L0 = 1; L0 <= 64; L0 += 16) {
+            uint32_t cl[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cl[u] = cntL[L0 + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                first[L0 + u] = c;
+                c = (c + cl[u]) << 1;
+                if (cl[u]) maxl = L0 + u;
+            }
         }
         dy->max_len = maxl;
         dy->n_used = m;
@@ -386,16 +394,25 @@ __global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
         uint64_t c = 0;
         uint32_t off = 0, maxl = 0;
         int bad = 0;
-        for (int L = 1; L <= 64; ++L) {
-            first[L] = c;
-            offs[L] = off;
-            off += cntL[L];
-            if (L <= kMaxDecodeLen && c + cntL[L] > (1ull << L)) bad = 1;
-            c = L <= kMaxDecodeLen ? (c + cntL[L]) << 1 : 0;
-            if (cntL[L]) maxl = L;
-            T->first[L] = first[L];
-            T->count[L] = cntL[L];
-            T->offset[L] = offs[L];
+        // counts read 16 at a time so that the chain waits on LDS four times
+        for (int L0 = 1; L0 <= 64; L0 += 16) {
+            uint32_t cl[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cl[u] = cntL[L0 + u];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int L = L0 + u;
+                const uint32_t n = cl[u];
+                first[L] = c;
+                offs[L] = off;
+                T->first[L] = c;
+                T->count[L] = n;
+                T->offset[L] = off;
+                off += n;
+                if (L <= kMaxDecodeLen && c + n > (1ull << L)) bad = 1;
+                c = L <= kMaxDecodeLen ? (c + n) << 1 : 0;
+                if (n) maxl = L;
+            }
         }
         T->first[0] = 0, T->count[0] = 0, T->offset[0] = 0;
         T->max_len = maxl;

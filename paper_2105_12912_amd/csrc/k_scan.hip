@@ -1,7 +1,9 @@
 // k_scan.hip -- exclusive prefix sum of a uint32 array (reduce-then-scan).
-// A first kernel writes every tile's sum; in the second, each workgroup adds
-// up the sums of the tiles before its own (a few loads per thread for the
-// tile counts used here) and scans its tile from there.
+// A first kernel writes every tile's sum.  Up to kScanDirect tiles, each
+// workgroup of the second kernel adds up the sums of the tiles before its own
+// (at most a few loads per thread) and scans its tile from there; above that
+// (the total work of those sums grows with the square of the tile count), one
+// workgroup scans the tile sums in between.
 //
 // Used for every offset computation of the path: ordered outlier positions
 // (per-segment counts), Huffman word offsets (per-chunk word counts), RLE run
@@ -16,6 +18,7 @@ namespace ebc {
 
 constexpr int kScanItems = 16;
 constexpr uint32_t kScanTile = kBlock * kScanItems;
+constexpr uint32_t kScanDirect = 1024;  // tiles up to which the tile sums are not scanned first
 
 // exclusive scan of one value per thread over the block; *total = block sum
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
@@ -71,6 +74,29 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restri
     }
 }
 
+// single block: exclusive scan of the block sums, total in sums[nb]
+__global__ __launch_bounds__(kBlock) void k_scan_top(uint32_t* __restrict__ sums, uint32_t nb)
+{
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += kScanTile) {
+        uint32_t v[kScanItems];
+        load_items(sums, nb, base, v);
+        uint32_t loc = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) loc += v[k];
+        uint32_t tot;
+        uint32_t off = block_excl_scan(loc, &tot) + carry;
+        const uint32_t i0 = base + threadIdx.x * kScanItems;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            if (i0 + k < nb) sums[i0 + k] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) sums[nb] = carry;
+}
+
 // total of an empty array
 __global__ void k_scan_empty(uint32_t* __restrict__ a) { a[0] = 0; }
 
@@ -87,13 +113,19 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v)
     return t;
 }
 
+// SCANNED: sums[] already holds the exclusive prefix of the tile sums
+template <bool SCANNED>
 __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, uint32_t n,
                                                       const uint32_t* __restrict__ sums,
                                                       uint32_t nb)
 {
     uint32_t pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) pre += sums[b];
-    pre = block_sum(pre);
+    if (SCANNED) {
+        pre = sums[blockIdx.x];
+    } else {
+        for (uint32_t b = threadIdx.x; b < blockIdx.x; b += kBlock) pre += sums[b];
+        pre = block_sum(pre);
+    }
     uint32_t v[kScanItems];
     const uint32_t base = blockIdx.x * kScanTile;
     load_items(a, n, base, v);
@@ -133,7 +165,12 @@ hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s)
     }
     const uint32_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, a, n, tmp);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kBlock), 0, s, a, n, tmp, nb);
+    if (nb <= kScanDirect) {
+        hipLaunchKernelGGL(k_scan_down<false>, dim3(nb), dim3(kBlock), 0, s, a, n, tmp, nb);
+    } else {
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);
+        hipLaunchKernelGGL(k_scan_down<true>, dim3(nb), dim3(kBlock), 0, s, a, n, tmp, nb);
+    }
     return hipGetLastError();
 }
 

@@ -152,6 +152,18 @@ def test_codewords_longer_than_32_bits(E):
         np.testing.assert_array_equal(bits(y), bits(O.decompress(ref)))
 
 
+def test_forced_rle_with_millions_of_runs(E):
+    """Run-length coding forced on noise: one run per element or so (4.8M
+    runs), so the run-start scan covers more tiles than the direct
+    down-sweep takes and goes through the scanned tile sums."""
+    x = np.random.default_rng(41).standard_normal(5_000_000).astype(np.float32)
+    ref = O.compress(x, 1e-2, codec="rle")
+    assert O.archive_info(ref)["n_a"] > 1024 * 4096
+    a = E.compress(dev(x), 1e-2, codec="rle")
+    assert a.cpu().numpy().tobytes() == ref
+    np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
+
+
 def test_constant_field(E):
     x = np.full((33, 45), -2.5, np.float32)
     a = E.compress(dev(x), 1e-4)

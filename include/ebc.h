@@ -68,6 +68,7 @@ extern "C" {
 #define EBC_ARC_HUFFMAN 0
 #define EBC_ARC_RLE 1
 #define EBC_ARC_CONST 2
+#define EBC_ARC_RLE_VLE 3  /* RLE with the run values Huffman-coded (Sec. III-A) */
 
 typedef struct ebc_params {
     int32_t eb_mode;     /* EBC_EB_ABS or EBC_EB_REL */

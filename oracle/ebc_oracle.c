@@ -26,7 +26,12 @@
  *     leaf wins ties (Sec. II-A step 6 only names "canonical"),
  *   - adaptive choice: RLE iff the Huffman average bit length <= 1.09,
  *     evaluated as the integer test 100*sum(f*len) <= 109*N
- *     (Sec. I contribution list, Sec. III-B.2).
+ *     (Sec. I contribution list, Sec. III-B.2),
+ *   - the workflow "RLE with optional VLE" (Sec. III-A): on request, the run
+ *     values are Huffman-coded with a codebook of their own; the run lengths
+ *     stay plain (the paper leaves that metadata uncoded by default),
+ *   - fp64 fields (Sec. III, where the Huffman ceiling is 64 for double) run
+ *     through the same integer core with a guard step sized for fp64 output.
  */
 #include <math.h>
 #include <stdint.h>
@@ -51,9 +56,10 @@ enum {
 };
 
 /* Archive codec byte and API codec request (two different enumerations). */
-enum { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2 };
-enum { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2 };
+enum { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2, ARC_RLE_VLE = 3 };
+enum { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2, REQ_RLE_VLE = 3, REQ_AUTO_VLE = 4 };
 enum { EB_ABS = 0, EB_REL = 1 };
+enum { DT_F32 = 0, DT_F64 = 1 };
 
 #define HDR_BYTES 128u
 
@@ -75,6 +81,28 @@ int ora_value_range(const float* x, uint64_t n, float* mn, float* mx)
         if (!isfinite(x[i])) return ORA_ERR_NONFINITE;
         if (less_total(x[i], lo)) lo = x[i];
         if (less_total(hi, x[i])) hi = x[i];
+    }
+    *mn = lo;
+    *mx = hi;
+    return ORA_OK;
+}
+
+/* C1 for fp64 fields: the same total order (-0 < +0). */
+static int less_total64(double a, double b)
+{
+    if (a < b) return 1;
+    if (a == b && a == 0.0 && signbit(a) && !signbit(b)) return 1;
+    return 0;
+}
+
+int ora_value_range64(const double* x, uint64_t n, double* mn, double* mx)
+{
+    if (!x || !mn || !mx || n == 0) return ORA_ERR_ARG;
+    double lo = x[0], hi = x[0];
+    for (uint64_t i = 0; i < n; ++i) {
+        if (!isfinite(x[i])) return ORA_ERR_NONFINITE;
+        if (less_total64(x[i], lo)) lo = x[i];
+        if (less_total64(hi, x[i])) hi = x[i];
     }
     *mn = lo;
     *mx = hi;
@@ -104,10 +132,38 @@ int ora_quant_step(double M, double eb_abs, double* ebx2, double* inv, int* e_ou
     return ORA_OK;
 }
 
+/* C2 for fp64 fields.  The output rounding is now 2^-53 relative, so the
+   guard needs eps >= 2^-50 (M/eb + 1): eps = 2^max(k - 48, -49) with
+   k = ilogb(M) - ilogb(eb_abs).  The codes must also stay far inside int32
+   (the 3D Lorenzo difference adds eight of them): k > 27 is rejected as a
+   bound too small for this code width. */
+int ora_quant_step64(double M, double eb_abs, double* ebx2, double* inv, int* e_out)
+{
+    if (!(eb_abs > 0.0) || !isfinite(eb_abs)) return ORA_ERR_EB_TOO_SMALL;
+    if (eb_abs > 0x1p1000) return ORA_ERR_EB;
+    int e = -49;
+    if (M != 0.0) {
+        int k = ilogb(M) - ilogb(eb_abs);
+        if (k > 27) return ORA_ERR_EB_TOO_SMALL;
+        if (k - 48 > e) e = k - 48;
+    }
+    double eps = ldexp(1.0, e);
+    double step = (eb_abs * (1.0 - eps)) * 2.0;
+    if (ebx2) *ebx2 = step;
+    if (inv) *inv = 1.0 / step;
+    if (e_out) *e_out = e;
+    return ORA_OK;
+}
+
 /* C3: prequantisation d = round(x / (2 eb)) as rint(x * inv) (Sec. IV-A.1). */
 void ora_prequant(const float* x, uint64_t n, double inv, int32_t* d)
 {
     for (uint64_t i = 0; i < n; ++i) d[i] = (int32_t)rint((double)x[i] * inv);
+}
+
+void ora_prequant64(const double* x, uint64_t n, double inv, int32_t* d)
+{
+    for (uint64_t i = 0; i < n; ++i) d[i] = (int32_t)rint(x[i] * inv);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -326,32 +382,34 @@ int ora_choose_rle(const uint64_t* hist, const uint8_t* len, uint32_t n_bins, ui
 /* ------------------------------------------------------------------------ */
 /* C10a: chunked Huffman encoding.  Chunks of hc symbols; each chunk starts  */
 /* on a 32-bit word; code bits are written MSB-first; bit 31 of a chunk's    */
-/* first word is its first bit; unused bits are zero.  Writes the chunk      */
-/* entry bits[c] for every chunk and, when words != NULL, the words in      */
-/* chunk order.  Returns the total word count.                               */
+/* first word is its first bit; unused bits are zero.                        */
 /*                                                                          */
-/* Chunk entry (container choice, not from the paper): the chunk's bit      */
-/* count; for hc <= 1024 the count is below 2^16 (lengths are at most 46    */
-/* for N < 2^32) and the high half holds the bit offset at which the        */
-/* chunk's symbol hc/2 starts (the bit count when the chunk is shorter), so */
-/* a decoder can start on both halves of a chunk at once.                   */
+/* Sub-chunk metadata (container choice, not from the paper): a chunk is cut */
+/* into sub-chunks of hs = min(hc, 256) symbols that follow each other in    */
+/* the chunk's bits without padding, and the bit count of every sub-chunk   */
+/* is stored as a u16 (at most 256 codewords of at most 64 bits: below      */
+/* 2^16).  The chunk's bit count is the sum of its sub-chunks', and every   */
+/* sub-chunk start is known, so a decoder can start on each one at once.    */
+/* Writes sbits for every sub-chunk and, when words != NULL, the words in   */
+/* chunk order.  Returns the total word count.                              */
 /* ------------------------------------------------------------------------ */
-uint32_t ora_chunk_bits(uint32_t entry, uint32_t hc) { return hc <= 1024 ? entry & 0xFFFFu : entry; }
+uint32_t ora_sub_chunk(uint32_t hc) { return hc < 256 ? hc : 256; }
 
 uint64_t ora_huffman_encode(const uint16_t* q, uint64_t n, const uint8_t* len,
-                            const uint64_t* code, uint32_t hc, uint32_t* bits, uint32_t* words)
+                            const uint64_t* code, uint32_t hc, uint16_t* sbits, uint32_t* words)
 {
+    uint32_t hs = ora_sub_chunk(hc);
     uint64_t nch = (n + hc - 1) / hc;
     uint64_t wbase = 0;
     for (uint64_t c = 0; c < nch; ++c) {
         uint64_t lo = c * hc, hi = lo + hc < n ? lo + hc : n;
-        uint64_t nb = 0, mid = 0;
-        for (uint64_t i = lo; i < hi; ++i) {
-            if (i == lo + hc / 2) mid = nb;
-            nb += len[q[i]];
+        uint64_t nb = 0;
+        for (uint64_t s0 = lo; s0 < hi; s0 += hs) {
+            uint64_t s1 = s0 + hs < hi ? s0 + hs : hi, sb = 0;
+            for (uint64_t i = s0; i < s1; ++i) sb += len[q[i]];
+            sbits[s0 / hs] = (uint16_t)sb;
+            nb += sb;
         }
-        if (hi - lo <= hc / 2) mid = nb;
-        bits[c] = hc <= 1024 ? (uint32_t)nb | ((uint32_t)mid << 16) : (uint32_t)nb;
         uint64_t nw = (nb + 31) / 32;
         if (words) {
             for (uint64_t w = 0; w < nw; ++w) words[wbase + w] = 0;
@@ -406,8 +464,9 @@ static int canon_build(canon_t* t, const uint8_t* len, uint32_t n_bins)
     return ORA_OK;
 }
 
-/* D2 (Huffman): decode min(hc, remaining) symbols per chunk, bit by bit. */
-int ora_huffman_decode(const uint32_t* bits, const uint32_t* words, uint64_t n_words, uint64_t n,
+/* D2 (Huffman): decode min(hc, remaining) symbols per chunk, bit by bit;  */
+/* every sub-chunk must take exactly its stored bit count.                   */
+int ora_huffman_decode(const uint16_t* sbits, const uint32_t* words, uint64_t n_words, uint64_t n,
                        uint32_t hc, const uint8_t* len, uint32_t n_bins, uint16_t* q)
 {
     canon_t t;
@@ -416,26 +475,32 @@ int ora_huffman_decode(const uint32_t* bits, const uint32_t* words, uint64_t n_w
         free(t.sorted);
         return st;
     }
+    uint32_t hs = ora_sub_chunk(hc);
     uint64_t nch = (n + hc - 1) / hc;
     uint64_t wbase = 0;
     for (uint64_t c = 0; c < nch && st == ORA_OK; ++c) {
         uint64_t lo = c * hc, hi = lo + hc < n ? lo + hc : n;
-        uint64_t nb = ora_chunk_bits(bits[c], hc), nw = (nb + 31) / 32;
-        uint64_t mid = hc <= 1024 ? bits[c] >> 16 : 0;
-        if (wbase + nw > n_words || (hc <= 1024 && hi - lo <= hc / 2 && mid != nb)) {
+        uint64_t nb = 0;
+        for (uint64_t s0 = lo; s0 < hi; s0 += hs) nb += sbits[s0 / hs];
+        uint64_t nw = (nb + 31) / 32;
+        if (wbase + nw > n_words) {
             st = ORA_ERR_ARCHIVE;
             break;
         }
-        uint64_t pos = 0;
+        uint64_t pos = 0, sub_end = 0;
         for (uint64_t i = lo; i < hi; ++i) {
-            if (hc <= 1024 && i == lo + hc / 2 && pos != mid) {
-                st = ORA_ERR_ARCHIVE;
-                break;
+            if ((i - lo) % hs == 0) {
+                /* a sub-chunk starts: the previous one must have ended exactly */
+                if (pos != sub_end) {
+                    st = ORA_ERR_ARCHIVE;
+                    break;
+                }
+                sub_end += sbits[i / hs];
             }
             uint64_t v = 0;
             int l = 0, found = 0;
             while (l < 64) {
-                if (pos >= nb) break;
+                if (pos >= sub_end) break;
                 uint32_t bit = (words[wbase + pos / 32] >> (31 - pos % 32)) & 1u;
                 ++pos;
                 ++l;
@@ -451,6 +516,7 @@ int ora_huffman_decode(const uint32_t* bits, const uint32_t* words, uint64_t n_w
                 break;
             }
         }
+        if (st == ORA_OK && pos != sub_end) st = ORA_ERR_ARCHIVE;
         wbase += nw;
     }
     free(t.sorted);
@@ -530,9 +596,26 @@ void ora_dequant(const int32_t* d, uint64_t n, double ebx2, float* out)
     for (uint64_t i = 0; i < n; ++i) out[i] = (float)((double)d[i] * ebx2);
 }
 
+/* D5 for fp64 fields: the product rounded once, in binary64. */
+void ora_dequant64(const int32_t* d, uint64_t n, double ebx2, double* out)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = (double)d[i] * ebx2;
+}
+
 /* ------------------------------------------------------------------------ */
-/* Archive format v1 (little-endian, 128-byte header, 16-byte aligned        */
+/* Archive format v2 (little-endian, 128-byte header, 16-byte aligned        */
 /* sections, zero padding).                                                  */
+/*   0 "EBC1", 4 version u16 = 2, 6 flags u16 = 0,                           */
+/*   8 rank, codec, eb_mode, dtype (u8 each), 12 n_bins u32,                 */
+/*  16 dims u64 x3, 40 Lorenzo chunk u32 x3, 52 hc u32,                      */
+/*  56 eb, eb_abs, ebx2 (f64), 80 constant value f64,                        */
+/*  88 n_outliers, 96 n_runs or n_chunks, 104 n_words (u64), 112 total u64,  */
+/* 120 hs (Huffman sub-chunk symbols) u32, 124 zero u32.                     */
+/* Sections: Huffman  u8 len[n_bins] | u16 sbits[n_sub] | u32 words        */
+/*           RLE      u16 val[R] | u32 rlen[R]                               */
+/*           RLE+VLE  u8 len[n_bins] | u16 sbits[n_sub(R)] | u32 words |     */
+/*                    u32 rlen[R]   (Huffman over the R run values)          */
+/*           all      u32 outlier_index[n_out] | i32 outlier_delta[n_out]    */
 /* ------------------------------------------------------------------------ */
 static uint64_t a16(uint64_t v) { return (v + 15u) & ~(uint64_t)15u; }
 
@@ -540,21 +623,19 @@ static void put_u16(uint8_t* p, uint16_t v) { memcpy(p, &v, 2); }
 static void put_u32(uint8_t* p, uint32_t v) { memcpy(p, &v, 4); }
 static void put_u64(uint8_t* p, uint64_t v) { memcpy(p, &v, 8); }
 static void put_f64(uint8_t* p, double v) { memcpy(p, &v, 8); }
-static void put_f32(uint8_t* p, float v) { memcpy(p, &v, 4); }
 static uint16_t get_u16(const uint8_t* p) { uint16_t v; memcpy(&v, p, 2); return v; }
 static uint32_t get_u32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
 static uint64_t get_u64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
 static double get_f64(const uint8_t* p) { double v; memcpy(&v, p, 8); return v; }
-static float get_f32(const uint8_t* p) { float v; memcpy(&v, p, 4); return v; }
 
 typedef struct {
-    int rank, codec, eb_mode;
+    int rank, codec, eb_mode, dtype;
     uint32_t n_bins;
     uint64_t dims[3];
     uint32_t chunk[3];
-    uint32_t hc;
+    uint32_t hc, hs;
     double eb, eb_abs, ebx2;
-    float cval;
+    double cval;
     uint64_t n_out, n_a, n_words, total;
 } hdr_t;
 
@@ -562,11 +643,12 @@ static void write_header(uint8_t* o, const hdr_t* h)
 {
     memset(o, 0, HDR_BYTES);
     memcpy(o, "EBC1", 4);
-    put_u16(o + 4, 1);
+    put_u16(o + 4, 2);
     put_u16(o + 6, 0);
     o[8] = (uint8_t)h->rank;
     o[9] = (uint8_t)h->codec;
     o[10] = (uint8_t)h->eb_mode;
+    o[11] = (uint8_t)h->dtype;
     put_u32(o + 12, h->n_bins);
     for (int k = 0; k < 3; ++k) put_u64(o + 16 + 8 * k, h->dims[k]);
     for (int k = 0; k < 3; ++k) put_u32(o + 40 + 4 * k, h->chunk[k]);
@@ -574,20 +656,22 @@ static void write_header(uint8_t* o, const hdr_t* h)
     put_f64(o + 56, h->eb);
     put_f64(o + 64, h->eb_abs);
     put_f64(o + 72, h->ebx2);
-    put_f32(o + 80, h->cval);
+    put_f64(o + 80, h->cval);
     put_u64(o + 88, h->n_out);
     put_u64(o + 96, h->n_a);
     put_u64(o + 104, h->n_words);
     put_u64(o + 112, h->total);
+    put_u32(o + 120, h->hs);
 }
 
 static int read_header(const uint8_t* a, uint64_t size, hdr_t* h)
 {
     if (!a || size < HDR_BYTES) return ORA_ERR_ARCHIVE;
-    if (memcmp(a, "EBC1", 4) != 0 || get_u16(a + 4) != 1) return ORA_ERR_ARCHIVE;
+    if (memcmp(a, "EBC1", 4) != 0 || get_u16(a + 4) != 2) return ORA_ERR_ARCHIVE;
     h->rank = a[8];
     h->codec = a[9];
     h->eb_mode = a[10];
+    h->dtype = a[11];
     h->n_bins = get_u32(a + 12);
     for (int k = 0; k < 3; ++k) h->dims[k] = get_u64(a + 16 + 8 * k);
     for (int k = 0; k < 3; ++k) h->chunk[k] = get_u32(a + 40 + 4 * k);
@@ -595,12 +679,13 @@ static int read_header(const uint8_t* a, uint64_t size, hdr_t* h)
     h->eb = get_f64(a + 56);
     h->eb_abs = get_f64(a + 64);
     h->ebx2 = get_f64(a + 72);
-    h->cval = get_f32(a + 80);
+    h->cval = get_f64(a + 80);
     h->n_out = get_u64(a + 88);
     h->n_a = get_u64(a + 96);
     h->n_words = get_u64(a + 104);
     h->total = get_u64(a + 112);
-    if (h->rank < 1 || h->rank > 3 || h->codec > 2) return ORA_ERR_ARCHIVE;
+    h->hs = get_u32(a + 120);
+    if (h->rank < 1 || h->rank > 3 || h->codec > 3 || h->dtype > 1) return ORA_ERR_ARCHIVE;
     if (h->total > size) return ORA_ERR_ARCHIVE;
     return ORA_OK;
 }
@@ -641,34 +726,97 @@ static uint32_t ceil_log2(uint32_t v)
     return b;
 }
 
-/* Worst case over both codecs: Huffman payload <= N*ceil(log2 n_bins) bits
-   (no worse than a fixed-length code) plus one partial word per chunk; RLE
-   <= N runs of 6 bytes; outliers <= N entries of 8 bytes. */
+/* Bytes of a Huffman-coded stream of m symbols (length table, sub-chunk bit
+   counts, words) at most: no more bits than a fixed-length code of
+   ceil(log2 n_bins) bits, plus one partial word per chunk. */
+static uint64_t huff_stream_bound(uint64_t m, uint32_t n_bins, uint32_t hc)
+{
+    uint64_t nch = (m + hc - 1) / hc, nsub = (m + ora_sub_chunk(hc) - 1) / ora_sub_chunk(hc);
+    return a16(n_bins) + a16(2 * nsub) + a16(4 * ((m * ceil_log2(n_bins) + 31) / 32 + nch));
+}
+
+/* Worst case over all codecs: a Huffman stream of N symbols; RLE <= N runs
+   of 6 bytes; RLE+VLE <= a Huffman stream of N run values plus N lengths;
+   outliers <= N entries of 8 bytes. */
 uint64_t ora_compress_bound(int rank, const uint64_t dims[3], uint32_t n_bins, uint32_t hc)
 {
     uint64_t n;
     if (validate(rank, dims, n_bins, hc, &n)) return 0;
-    uint64_t nch = (n + hc - 1) / hc;
-    uint64_t huff = a16(n_bins) + a16(4 * nch) + a16(4 * ((n * ceil_log2(n_bins) + 31) / 32 + nch));
+    uint64_t huff = huff_stream_bound(n, n_bins, hc);
     uint64_t rle = a16(2 * n) + a16(4 * n);
-    return HDR_BYTES + (huff > rle ? huff : rle) + a16(4 * n) + a16(4 * n);
+    uint64_t rv = huff + a16(4 * n);
+    uint64_t m = huff > rle ? huff : rle;
+    if (rv > m) m = rv;
+    return HDR_BYTES + m + a16(4 * n) + a16(4 * n);
+}
+
+/* Huffman coding of a symbol stream s[m] over n_bins symbols into
+   o = len | sbits | words (section offsets from `base`); returns the words.
+   Used for the codes themselves (Huffman codec) and for the run values
+   (RLE+VLE codec); each stream has a codebook of its own. */
+typedef struct {
+    uint64_t off_len, off_sbits, off_words, end, n_words;
+} hsec_t;
+
+static int huff_stream(const uint16_t* s, uint64_t m, uint32_t n_bins, uint32_t hc, uint64_t base,
+                       uint8_t* o, uint64_t cap, hsec_t* sec)
+{
+    uint64_t* hist = (uint64_t*)malloc(sizeof(uint64_t) * n_bins);
+    uint8_t* len = (uint8_t*)malloc(n_bins);
+    uint64_t* code = (uint64_t*)malloc(sizeof(uint64_t) * n_bins);
+    uint32_t hs = ora_sub_chunk(hc);
+    uint64_t nsub = (m + hs - 1) / hs;
+    uint16_t* sb = (uint16_t*)malloc(2 * (nsub ? nsub : 1));
+    uint32_t* words = NULL;
+    int st = ORA_OK;
+    if (!hist || !len || !code || !sb) {
+        st = ORA_ERR_NOMEM;
+        goto out;
+    }
+    ora_histogram(s, m, n_bins, hist);
+    st = ora_huffman_lengths(hist, n_bins, len);
+    if (st) goto out;
+    ora_canonical_codes(len, n_bins, code);
+    sec->n_words = ora_huffman_encode(s, m, len, code, hc, sb, NULL);
+    sec->off_len = base;
+    sec->off_sbits = a16(base + n_bins);
+    sec->off_words = a16(sec->off_sbits + 2 * nsub);
+    sec->end = a16(sec->off_words + 4 * sec->n_words);
+    if (!o) goto out;
+    if (sec->end > cap) {
+        st = ORA_ERR_OUT_TOO_SMALL;
+        goto out;
+    }
+    words = (uint32_t*)malloc(4 * (sec->n_words ? sec->n_words : 1));
+    if (!words) {
+        st = ORA_ERR_NOMEM;
+        goto out;
+    }
+    ora_huffman_encode(s, m, len, code, hc, sb, words);
+    memcpy(o + sec->off_len, len, n_bins);
+    memcpy(o + sec->off_sbits, sb, 2 * nsub);
+    memcpy(o + sec->off_words, words, 4 * sec->n_words);
+out:
+    free(hist), free(len), free(code), free(sb), free(words);
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */
-/* Whole compression pipeline (C0..C11).                                     */
-/* chunk == NULL selects the default chunk for the rank.                     */
+/* Whole compression pipeline (C0..C11).  x points at N fp32 (dtype 0) or   */
+/* fp64 (dtype 1) values.  chunk == NULL selects the default Lorenzo chunk. */
 /* ------------------------------------------------------------------------ */
-int ora_compress(const float* x, int rank, const uint64_t dims[3], int eb_mode, double eb,
-                 uint32_t n_bins, int codec_req, uint32_t hc, const uint32_t* chunk_in,
+int ora_compress(const void* x, int dtype, int rank, const uint64_t dims[3], int eb_mode,
+                 double eb, uint32_t n_bins, int codec_req, uint32_t hc, const uint32_t* chunk_in,
                  uint8_t* out, uint64_t cap, uint64_t* size)
 {
     uint64_t n;
     if (!x || !out || !size) return ORA_ERR_ARG;
+    if (dtype != DT_F32 && dtype != DT_F64) return ORA_ERR_ARG;
     int st = validate(rank, dims, n_bins, hc, &n);
     if (st) return st;
     if (!(eb > 0.0) || !isfinite(eb)) return ORA_ERR_EB;
     if (eb_mode != EB_ABS && eb_mode != EB_REL) return ORA_ERR_ARG;
-    if (codec_req < REQ_AUTO || codec_req > REQ_RLE) return ORA_ERR_ARG;
+    if (codec_req < REQ_AUTO || codec_req > REQ_AUTO_VLE) return ORA_ERR_ARG;
     uint32_t chunk[3];
     if (chunk_in) memcpy(chunk, chunk_in, sizeof(chunk));
     else default_chunk(rank, chunk);
@@ -679,17 +827,24 @@ int ora_compress(const float* x, int rank, const uint64_t dims[3], int eb_mode, 
     memset(&h, 0, sizeof(h));
     h.rank = rank;
     h.eb_mode = eb_mode;
+    h.dtype = dtype;
     h.n_bins = n_bins;
     memcpy(h.dims, dims, sizeof(h.dims));
     memcpy(h.chunk, chunk, sizeof(h.chunk));
     h.hc = hc;
     h.eb = eb;
 
-    float mn, mx;
-    st = ora_value_range(x, n, &mn, &mx);
+    double mn, mx;
+    if (dtype == DT_F32) {
+        float a, b;
+        st = ora_value_range((const float*)x, n, &a, &b);
+        mn = a, mx = b;
+    } else {
+        st = ora_value_range64((const double*)x, n, &mn, &mx);
+    }
     if (st) return st;
-    double range = (double)mx - (double)mn;
-    double M = fabs((double)mn) > fabs((double)mx) ? fabs((double)mn) : fabs((double)mx);
+    double range = mx - mn; /* exact for fp32 ends; rounded once for fp64 ends */
+    double M = fabs(mn) > fabs(mx) ? fabs(mn) : fabs(mx);
 
     if (eb_mode == EB_REL && range == 0.0) {
         h.codec = ARC_CONST;
@@ -702,7 +857,8 @@ int ora_compress(const float* x, int rank, const uint64_t dims[3], int eb_mode, 
     }
     h.eb_abs = eb_mode == EB_REL ? eb * range : eb;
     double inv;
-    st = ora_quant_step(M, h.eb_abs, &h.ebx2, &inv, NULL);
+    st = dtype == DT_F32 ? ora_quant_step(M, h.eb_abs, &h.ebx2, &inv, NULL)
+                         : ora_quant_step64(M, h.eb_abs, &h.ebx2, &inv, NULL);
     if (st) return st;
 
     int32_t* d = (int32_t*)malloc(sizeof(int32_t) * n);
@@ -710,14 +866,16 @@ int ora_compress(const float* x, int rank, const uint64_t dims[3], int eb_mode, 
     uint16_t* q = (uint16_t*)malloc(sizeof(uint16_t) * n);
     uint64_t* hist = (uint64_t*)malloc(sizeof(uint64_t) * n_bins);
     uint8_t* len = (uint8_t*)malloc(n_bins);
-    uint64_t* code = (uint64_t*)malloc(sizeof(uint64_t) * n_bins);
     uint32_t* oidx = NULL;
     int32_t* oval = NULL;
-    if (!d || !delta || !q || !hist || !len || !code) {
+    uint16_t* val = NULL;
+    uint32_t* rl = NULL;
+    if (!d || !delta || !q || !hist || !len) {
         st = ORA_ERR_NOMEM;
         goto done;
     }
-    ora_prequant(x, n, inv, d);
+    if (dtype == DT_F32) ora_prequant((const float*)x, n, inv, d);
+    else ora_prequant64((const double*)x, n, inv, d);
     ora_lorenzo(d, rank, dims, chunk, delta);
     h.n_out = ora_postquant(delta, n, n_bins, q, NULL, NULL);
     oidx = (uint32_t*)malloc(sizeof(uint32_t) * (h.n_out ? h.n_out : 1));
@@ -730,78 +888,86 @@ int ora_compress(const float* x, int rank, const uint64_t dims[3], int eb_mode, 
     ora_histogram(q, n, n_bins, hist);
     st = ora_huffman_lengths(hist, n_bins, len);
     if (st) goto done;
-    ora_canonical_codes(len, n_bins, code);
-    if (codec_req == REQ_AUTO) h.codec = ora_choose_rle(hist, len, n_bins, n) ? ARC_RLE : ARC_HUFFMAN;
-    else h.codec = codec_req == REQ_RLE ? ARC_RLE : ARC_HUFFMAN;
-
+    {
+        int rle = ora_choose_rle(hist, len, n_bins, n);
+        switch (codec_req) {
+        case REQ_AUTO: h.codec = rle ? ARC_RLE : ARC_HUFFMAN; break;
+        case REQ_AUTO_VLE: h.codec = rle ? ARC_RLE_VLE : ARC_HUFFMAN; break;
+        case REQ_HUFFMAN: h.codec = ARC_HUFFMAN; break;
+        case REQ_RLE: h.codec = ARC_RLE; break;
+        default: h.codec = ARC_RLE_VLE; break;
+        }
+    }
     uint64_t off_o;
     if (h.codec == ARC_HUFFMAN) {
-        uint64_t nch = (n + hc - 1) / hc;
-        uint32_t* bits = (uint32_t*)malloc(sizeof(uint32_t) * nch);
-        if (!bits) {
-            st = ORA_ERR_NOMEM;
-            goto done;
-        }
-        h.n_a = nch;
-        h.n_words = ora_huffman_encode(q, n, len, code, hc, bits, NULL);
-        uint64_t off_bits = a16(HDR_BYTES + n_bins);
-        uint64_t off_words = a16(off_bits + 4 * nch);
-        off_o = a16(off_words + 4 * h.n_words);
+        hsec_t sec;
+        h.n_a = (n + hc - 1) / hc;
+        h.hs = ora_sub_chunk(hc);
+        st = huff_stream(q, n, n_bins, hc, HDR_BYTES, NULL, 0, &sec);
+        if (st) goto done;
+        h.n_words = sec.n_words;
+        off_o = sec.end;
         h.total = a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out);
         if (h.total > cap) {
-            free(bits);
             st = ORA_ERR_OUT_TOO_SMALL;
             goto done;
         }
         memset(out, 0, h.total);
-        memcpy(out + HDR_BYTES, len, n_bins);
-        memcpy(out + off_bits, bits, 4 * nch);
-        uint32_t* words = (uint32_t*)malloc(sizeof(uint32_t) * (h.n_words ? h.n_words : 1));
-        if (!words) {
-            free(bits);
-            st = ORA_ERR_NOMEM;
-            goto done;
-        }
-        ora_huffman_encode(q, n, len, code, hc, bits, words);
-        memcpy(out + off_words, words, 4 * h.n_words);
-        free(words);
-        free(bits);
+        st = huff_stream(q, n, n_bins, hc, HDR_BYTES, out, cap, &sec);
+        if (st) goto done;
     } else {
         h.n_a = ora_rle_encode(q, n, NULL, NULL);
-        h.n_words = 0;
-        uint64_t off_len = a16(HDR_BYTES + 2 * h.n_a);
-        off_o = a16(off_len + 4 * h.n_a);
-        h.total = a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out);
-        if (h.total > cap) {
-            st = ORA_ERR_OUT_TOO_SMALL;
-            goto done;
-        }
-        uint16_t* val = (uint16_t*)malloc(2 * h.n_a);
-        uint32_t* rl = (uint32_t*)malloc(4 * h.n_a);
+        val = (uint16_t*)malloc(2 * h.n_a);
+        rl = (uint32_t*)malloc(4 * h.n_a);
         if (!val || !rl) {
-            free(val), free(rl);
             st = ORA_ERR_NOMEM;
             goto done;
         }
         ora_rle_encode(q, n, val, rl);
-        memset(out, 0, h.total);
-        memcpy(out + HDR_BYTES, val, 2 * h.n_a);
-        memcpy(out + off_len, rl, 4 * h.n_a);
-        free(val), free(rl);
+        if (h.codec == ARC_RLE) {
+            uint64_t off_len = a16(HDR_BYTES + 2 * h.n_a);
+            off_o = a16(off_len + 4 * h.n_a);
+            h.total = a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out);
+            if (h.total > cap) {
+                st = ORA_ERR_OUT_TOO_SMALL;
+                goto done;
+            }
+            memset(out, 0, h.total);
+            memcpy(out + HDR_BYTES, val, 2 * h.n_a);
+            memcpy(out + off_len, rl, 4 * h.n_a);
+        } else {
+            /* RLE+VLE: the run values as a Huffman stream of their own */
+            hsec_t sec;
+            h.hs = ora_sub_chunk(hc);
+            st = huff_stream(val, h.n_a, n_bins, hc, HDR_BYTES, NULL, 0, &sec);
+            if (st) goto done;
+            h.n_words = sec.n_words;
+            uint64_t off_len = sec.end;
+            off_o = a16(off_len + 4 * h.n_a);
+            h.total = a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out);
+            if (h.total > cap) {
+                st = ORA_ERR_OUT_TOO_SMALL;
+                goto done;
+            }
+            memset(out, 0, h.total);
+            st = huff_stream(val, h.n_a, n_bins, hc, HDR_BYTES, out, cap, &sec);
+            if (st) goto done;
+            memcpy(out + off_len, rl, 4 * h.n_a);
+        }
     }
     memcpy(out + off_o, oidx, 4 * h.n_out);
     memcpy(out + a16(off_o + 4 * h.n_out), oval, 4 * h.n_out);
     write_header(out, &h);
     *size = h.total;
 done:
-    free(d), free(delta), free(q), free(hist), free(len), free(code), free(oidx), free(oval);
+    free(d), free(delta), free(q), free(hist), free(len), free(oidx), free(oval), free(val), free(rl);
     return st;
 }
 
 /* Header fields for the Python side (n_elems = product of dims). */
 int ora_archive_info(const uint8_t* a, uint64_t size, int* rank, uint64_t dims[3], int* codec,
                      uint32_t* n_bins, uint64_t* n_out, uint64_t* n_a, uint64_t* n_words,
-                     double* ebx2)
+                     double* ebx2, int* dtype, uint32_t* hc)
 {
     hdr_t h;
     int st = read_header(a, size, &h);
@@ -814,13 +980,28 @@ int ora_archive_info(const uint8_t* a, uint64_t size, int* rank, uint64_t dims[3
     if (n_a) *n_a = h.n_a;
     if (n_words) *n_words = h.n_words;
     if (ebx2) *ebx2 = h.ebx2;
+    if (dtype) *dtype = h.dtype;
+    if (hc) *hc = h.hc;
     return ORA_OK;
 }
 
+/* Section offsets of a Huffman stream of m symbols starting at base. */
+static void huff_layout(uint64_t m, uint32_t n_bins, uint32_t hc, uint64_t n_words, uint64_t base,
+                        hsec_t* sec)
+{
+    uint64_t nsub = (m + ora_sub_chunk(hc) - 1) / ora_sub_chunk(hc);
+    sec->off_len = base;
+    sec->off_sbits = a16(base + n_bins);
+    sec->off_words = a16(sec->off_sbits + 2 * nsub);
+    sec->end = a16(sec->off_words + 4 * n_words);
+    sec->n_words = n_words;
+}
+
 /* ------------------------------------------------------------------------ */
-/* Whole decompression pipeline (D1..D5).                                    */
+/* Whole decompression pipeline (D1..D5).  out receives N fp32 or fp64       */
+/* values according to the archive's dtype.                                 */
 /* ------------------------------------------------------------------------ */
-int ora_decompress(const uint8_t* a, uint64_t size, float* out, uint64_t n_out_elems)
+int ora_decompress(const uint8_t* a, uint64_t size, void* out, uint64_t n_out_elems)
 {
     hdr_t h;
     int st = read_header(a, size, &h);
@@ -831,49 +1012,76 @@ int ora_decompress(const uint8_t* a, uint64_t size, float* out, uint64_t n_out_e
     if (st) return ORA_ERR_ARCHIVE;
     if (n_out_elems < n || !out) return ORA_ERR_OUT_TOO_SMALL;
     if (h.codec == ARC_CONST) {
-        for (uint64_t i = 0; i < n; ++i) out[i] = h.cval;
+        for (uint64_t i = 0; i < n; ++i) {
+            if (h.dtype == DT_F32) ((float*)out)[i] = (float)h.cval;
+            else ((double*)out)[i] = h.cval;
+        }
         return ORA_OK;
     }
+    if (h.codec != ARC_RLE && h.hs != ora_sub_chunk(h.hc)) return ORA_ERR_ARCHIVE;
     uint16_t* q = (uint16_t*)malloc(2 * n);
     int32_t* qp = (int32_t*)malloc(4 * n);
     int32_t* d = (int32_t*)malloc(4 * n);
+    uint16_t* val = NULL;
     if (!q || !qp || !d) {
         st = ORA_ERR_NOMEM;
         goto done;
     }
     uint64_t off_o;
     if (h.codec == ARC_HUFFMAN) {
-        uint64_t nch = (n + h.hc - 1) / h.hc;
-        if (h.n_a != nch) {
+        hsec_t sec;
+        if (h.n_a != (n + h.hc - 1) / h.hc) {
             st = ORA_ERR_ARCHIVE;
             goto done;
         }
-        uint64_t off_bits = a16(HDR_BYTES + h.n_bins);
-        uint64_t off_words = a16(off_bits + 4 * nch);
-        off_o = a16(off_words + 4 * h.n_words);
+        huff_layout(n, h.n_bins, h.hc, h.n_words, HDR_BYTES, &sec);
+        off_o = sec.end;
         if (a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out) > size) {
             st = ORA_ERR_ARCHIVE;
             goto done;
         }
-        st = ora_huffman_decode((const uint32_t*)(a + off_bits), (const uint32_t*)(a + off_words),
-                                h.n_words, n, h.hc, a + HDR_BYTES, h.n_bins, q);
-    } else {
+        st = ora_huffman_decode((const uint16_t*)(a + sec.off_sbits), (const uint32_t*)(a + sec.off_words),
+                                h.n_words, n, h.hc, a + sec.off_len, h.n_bins, q);
+    } else if (h.codec == ARC_RLE) {
         uint64_t off_len = a16(HDR_BYTES + 2 * h.n_a);
         off_o = a16(off_len + 4 * h.n_a);
-        if (a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out) > size) {
+        if (h.n_a > n || a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out) > size) {
             st = ORA_ERR_ARCHIVE;
             goto done;
         }
         st = ora_rle_decode((const uint16_t*)(a + HDR_BYTES), (const uint32_t*)(a + off_len), h.n_a,
                             n, q);
+    } else {
+        /* RLE+VLE: decode the run values, then expand the runs */
+        hsec_t sec;
+        if (h.n_a == 0 || h.n_a > n) {
+            st = ORA_ERR_ARCHIVE;
+            goto done;
+        }
+        huff_layout(h.n_a, h.n_bins, h.hc, h.n_words, HDR_BYTES, &sec);
+        uint64_t off_len = sec.end;
+        off_o = a16(off_len + 4 * h.n_a);
+        if (a16(a16(off_o + 4 * h.n_out) + 4 * h.n_out) > size) {
+            st = ORA_ERR_ARCHIVE;
+            goto done;
+        }
+        val = (uint16_t*)malloc(2 * h.n_a);
+        if (!val) {
+            st = ORA_ERR_NOMEM;
+            goto done;
+        }
+        st = ora_huffman_decode((const uint16_t*)(a + sec.off_sbits), (const uint32_t*)(a + sec.off_words),
+                                h.n_words, h.n_a, h.hc, a + sec.off_len, h.n_bins, val);
+        if (!st) st = ora_rle_decode(val, (const uint32_t*)(a + off_len), h.n_a, n, q);
     }
     if (st) goto done;
     st = ora_fuse(q, n, h.n_bins, (const uint32_t*)(a + off_o),
                   (const int32_t*)(a + a16(off_o + 4 * h.n_out)), h.n_out, qp);
     if (st) goto done;
     ora_reconstruct(qp, h.rank, h.dims, h.chunk, d);
-    ora_dequant(d, n, h.ebx2, out);
+    if (h.dtype == DT_F32) ora_dequant(d, n, h.ebx2, (float*)out);
+    else ora_dequant64(d, n, h.ebx2, (double*)out);
 done:
-    free(q), free(qp), free(d);
+    free(q), free(qp), free(d), free(val);
     return st;
 }

@@ -24,9 +24,12 @@ ERR = {
     -7: "OUT_TOO_SMALL", -8: "WS_TOO_SMALL", -9: "ARCHIVE", -10: "HIP", -11: "UNSUPPORTED",
     -12: "NOMEM",
 }
-ARC_HUFFMAN, ARC_RLE, ARC_CONST = 0, 1, 2
-REQ_AUTO, REQ_HUFFMAN, REQ_RLE = 0, 1, 2
+ARC_HUFFMAN, ARC_RLE, ARC_CONST, ARC_RLE_VLE = 0, 1, 2, 3
+REQ_AUTO, REQ_HUFFMAN, REQ_RLE, REQ_RLE_VLE, REQ_AUTO_VLE = 0, 1, 2, 3, 4
+CODEC_REQ = {"auto": REQ_AUTO, "huffman": REQ_HUFFMAN, "rle": REQ_RLE, "rle_vle": REQ_RLE_VLE,
+             "auto_vle": REQ_AUTO_VLE}
 EB_ABS, EB_REL = 0, 1
+DT_F32, DT_F64 = 0, 1
 HDR_BYTES = 128
 
 
@@ -59,8 +62,12 @@ def lib():
         u64, u32, i32, f64 = C.c_uint64, C.c_uint32, C.c_int, C.c_double
         sig = {
             "ora_value_range": (i32, [P, u64, P, P]),
+            "ora_value_range64": (i32, [P, u64, P, P]),
             "ora_quant_step": (i32, [f64, f64, P, P, P]),
+            "ora_quant_step64": (i32, [f64, f64, P, P, P]),
             "ora_prequant": (None, [P, u64, f64, P]),
+            "ora_prequant64": (None, [P, u64, f64, P]),
+            "ora_sub_chunk": (u32, [u32]),
             "ora_lorenzo": (None, [P, i32, P, P, P]),
             "ora_postquant": (u64, [P, u64, u32, P, P, P]),
             "ora_histogram": (None, [P, u64, u32, P]),
@@ -74,10 +81,11 @@ def lib():
             "ora_fuse": (i32, [P, u64, u32, P, P, u64, P]),
             "ora_reconstruct": (None, [P, i32, P, P, P]),
             "ora_dequant": (None, [P, u64, f64, P]),
+            "ora_dequant64": (None, [P, u64, f64, P]),
             "ora_compress_bound": (u64, [i32, P, u32, u32]),
-            "ora_compress": (i32, [P, i32, P, i32, f64, u32, i32, u32, P, P, u64, P]),
+            "ora_compress": (i32, [P, i32, i32, P, i32, f64, u32, i32, u32, P, P, u64, P]),
             "ora_decompress": (i32, [P, u64, P, u64]),
-            "ora_archive_info": (i32, [P, u64, P, P, P, P, P, P, P, P]),
+            "ora_archive_info": (i32, [P, u64, P, P, P, P, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -108,21 +116,35 @@ def _check(st, what):
 
 # ----------------------------------------------------------------- steps
 
+def _is64(x) -> bool:
+    return np.asarray(x).dtype == np.float64
+
+
 def value_range(x: np.ndarray):
+    if _is64(x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        mn, mx = C.c_double(), C.c_double()
+        _check(lib().ora_value_range64(_p(x), x.size, C.byref(mn), C.byref(mx)), "value_range")
+        return np.float64(mn.value), np.float64(mx.value)
     x = np.ascontiguousarray(x, dtype=np.float32)
     mn, mx = C.c_float(), C.c_float()
     _check(lib().ora_value_range(_p(x), x.size, C.byref(mn), C.byref(mx)), "value_range")
     return np.float32(mn.value), np.float32(mx.value)
 
 
-def quant_step(M: float, eb_abs: float):
+def quant_step(M: float, eb_abs: float, fp64: bool = False):
     ebx2, inv, e = C.c_double(), C.c_double(), C.c_int()
-    _check(lib().ora_quant_step(float(M), float(eb_abs), C.byref(ebx2), C.byref(inv),
-                                C.byref(e)), "quant_step")
+    fn = lib().ora_quant_step64 if fp64 else lib().ora_quant_step
+    _check(fn(float(M), float(eb_abs), C.byref(ebx2), C.byref(inv), C.byref(e)), "quant_step")
     return ebx2.value, inv.value, e.value
 
 
 def prequant(x: np.ndarray, inv: float) -> np.ndarray:
+    if _is64(x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        d = np.empty(x.shape, dtype=np.int32)
+        lib().ora_prequant64(_p(x), x.size, float(inv), _p(d))
+        return d
     x = np.ascontiguousarray(x, dtype=np.float32)
     d = np.empty(x.shape, dtype=np.int32)
     lib().ora_prequant(_p(x), x.size, float(inv), _p(d))
@@ -176,18 +198,25 @@ def choose_rle(hist: np.ndarray, length: np.ndarray, n: int) -> bool:
     return bool(lib().ora_choose_rle(_p(hist), _p(length), hist.size, int(n)))
 
 
+def sub_chunk(hc: int) -> int:
+    """Symbols per Huffman sub-chunk (the unit of the stored bit counts)."""
+    return int(lib().ora_sub_chunk(hc))
+
+
 def huffman_encode(q: np.ndarray, length: np.ndarray, code: np.ndarray, hc: int = 1024):
+    """Returns (sbits, words): u16 bit count per sub-chunk, u32 words."""
     q = np.ascontiguousarray(q, dtype=np.uint16).ravel()
-    nch = (q.size + hc - 1) // hc
-    bits = np.empty(nch, dtype=np.uint32)
+    hs = sub_chunk(hc)
+    nsub = (q.size + hs - 1) // hs
+    bits = np.empty(max(nsub, 1), dtype=np.uint16)
     nw = lib().ora_huffman_encode(_p(q), q.size, _p(length), _p(code), hc, _p(bits), None)
     words = np.empty(max(nw, 1), dtype=np.uint32)
     lib().ora_huffman_encode(_p(q), q.size, _p(length), _p(code), hc, _p(bits), _p(words))
-    return bits, words[:nw]
+    return bits[:nsub], words[:nw]
 
 
 def huffman_decode(bits, words, n: int, length, hc: int = 1024) -> np.ndarray:
-    bits = np.ascontiguousarray(bits, dtype=np.uint32)
+    bits = np.ascontiguousarray(bits, dtype=np.uint16)
     words = np.ascontiguousarray(words, dtype=np.uint32)
     length = np.ascontiguousarray(length, dtype=np.uint8)
     q = np.empty(n, dtype=np.uint16)
@@ -234,10 +263,10 @@ def reconstruct(qp: np.ndarray, rank: int, chunk=None) -> np.ndarray:
     return d
 
 
-def dequant(d: np.ndarray, ebx2: float) -> np.ndarray:
+def dequant(d: np.ndarray, ebx2: float, fp64: bool = False) -> np.ndarray:
     d = np.ascontiguousarray(d, dtype=np.int32)
-    out = np.empty(d.shape, dtype=np.float32)
-    lib().ora_dequant(_p(d), d.size, float(ebx2), _p(out))
+    out = np.empty(d.shape, dtype=np.float64 if fp64 else np.float32)
+    (lib().ora_dequant64 if fp64 else lib().ora_dequant)(_p(d), d.size, float(ebx2), _p(out))
     return out
 
 
@@ -249,51 +278,55 @@ def compress_bound(rank: int, dims, n_bins: int = 1024, hc: int = 1024) -> int:
 
 def compress(x: np.ndarray, eb: float, mode: str = "rel", n_bins: int = 1024,
              codec: str = "auto", hc: int = 1024, chunk=None, rank: int | None = None) -> bytes:
-    """Whole compression pipeline; returns the archive bytes."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
+    """Whole compression pipeline; returns the archive bytes.  x is fp32, or
+    fp64 (an fp64 archive)."""
+    fp64 = _is64(x)
+    x = np.ascontiguousarray(x, dtype=np.float64 if fp64 else np.float32)
     rank = rank or x.ndim
     dims = _dims(x.shape[::-1])
     cap = max(compress_bound(rank, dims[:rank], n_bins, hc), HDR_BYTES)
     out = np.empty(cap, dtype=np.uint8)
     size = C.c_uint64()
     ch = None if chunk is None else _p(np.array(chunk, dtype=np.uint32))
-    req = {"auto": REQ_AUTO, "huffman": REQ_HUFFMAN, "rle": REQ_RLE}[codec]
-    st = lib().ora_compress(_p(x), rank, _p(dims), EB_REL if mode == "rel" else EB_ABS,
-                            float(eb), n_bins, req, hc, ch, _p(out), cap, C.byref(size))
+    st = lib().ora_compress(_p(x), DT_F64 if fp64 else DT_F32, rank, _p(dims),
+                            EB_REL if mode == "rel" else EB_ABS, float(eb), n_bins,
+                            CODEC_REQ[codec], hc, ch, _p(out), cap, C.byref(size))
     _check(st, "compress")
     return out[: size.value].tobytes()
 
 
 def compress_status(x: np.ndarray, eb: float, mode: str = "rel", n_bins: int = 1024,
-                    rank: int | None = None, dims=None) -> int:
+                    rank: int | None = None, dims=None, codec: str = "auto", hc: int = 1024) -> int:
     """Status of a compression attempt (for error-path tests)."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
+    fp64 = _is64(x)
+    x = np.ascontiguousarray(x, dtype=np.float64 if fp64 else np.float32)
     rank = rank if rank is not None else x.ndim
     d = _dims(dims if dims is not None else x.shape[::-1])
-    out = np.empty(max(16 * x.size + 4096, 256), dtype=np.uint8)
+    out = np.empty(max(24 * x.size + 4096, 256), dtype=np.uint8)
     size = C.c_uint64()
-    return lib().ora_compress(_p(x), rank, _p(d), EB_REL if mode == "rel" else EB_ABS, float(eb),
-                              n_bins, REQ_AUTO, 1024, None, _p(out), out.size, C.byref(size))
+    return lib().ora_compress(_p(x), DT_F64 if fp64 else DT_F32, rank, _p(d),
+                              EB_REL if mode == "rel" else EB_ABS, float(eb), n_bins,
+                              CODEC_REQ[codec], hc, None, _p(out), out.size, C.byref(size))
 
 
 def archive_info(a: bytes) -> dict:
     buf = np.frombuffer(a, dtype=np.uint8)
-    rank, codec, nb = C.c_int(), C.c_int(), C.c_uint32()
+    rank, codec, nb, dt, hc = C.c_int(), C.c_int(), C.c_uint32(), C.c_int(), C.c_uint32()
     dims = np.zeros(3, dtype=np.uint64)
     no, na, nw, ebx2 = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_double()
     _check(lib().ora_archive_info(_p(buf), buf.size, C.byref(rank), _p(dims), C.byref(codec),
                                   C.byref(nb), C.byref(no), C.byref(na), C.byref(nw),
-                                  C.byref(ebx2)), "archive_info")
+                                  C.byref(ebx2), C.byref(dt), C.byref(hc)), "archive_info")
     return dict(rank=rank.value, dims=tuple(int(v) for v in dims), codec=codec.value,
                 n_bins=nb.value, n_outliers=no.value, n_a=na.value, n_words=nw.value,
-                ebx2=ebx2.value)
+                ebx2=ebx2.value, dtype=dt.value, hc=hc.value)
 
 
 def decompress(a: bytes) -> np.ndarray:
     info = archive_info(a)
     nx, ny, nz = info["dims"]
     shape = {1: (nx,), 2: (ny, nx), 3: (nz, ny, nx)}[info["rank"]]
-    out = np.empty(shape, dtype=np.float32)
+    out = np.empty(shape, dtype=np.float64 if info["dtype"] == DT_F64 else np.float32)
     buf = np.frombuffer(a, dtype=np.uint8)
     _check(lib().ora_decompress(_p(buf), buf.size, _p(out), out.size), "decompress")
     return out
@@ -306,38 +339,56 @@ def decompress_status(a: bytes) -> int:
         n = int(np.prod(info["dims"]))
     except OracleError as e:
         return e.status
-    out = np.empty(max(n, 1), dtype=np.float32)
+    out = np.empty(max(n, 1), dtype=np.float64)
     return lib().ora_decompress(_p(buf), buf.size, _p(out), out.size)
 
 
+def _a16(v):
+    return (v + 15) & ~15
+
+
+def huffman_layout(m: int, n_bins: int, hc: int, n_words: int, base: int = HDR_BYTES) -> dict:
+    """Section offsets of a Huffman stream of m symbols (format v2)."""
+    hs = sub_chunk(hc)
+    nsub = (m + hs - 1) // hs
+    ol = base
+    ob = _a16(ol + n_bins)
+    ow = _a16(ob + 2 * nsub)
+    return dict(len=ol, sbits=ob, words=ow, end=_a16(ow + 4 * n_words), n_sub=nsub)
+
+
 def sections(a: bytes) -> dict:
-    """Split an archive into its named arrays (format v1 layout)."""
+    """Split an archive into its named arrays (format v2 layout)."""
     info = archive_info(a)
     buf = np.frombuffer(a, dtype=np.uint8)
-
-    def a16(v):
-        return (v + 15) & ~15
-
     nb, no = info["n_bins"], info["n_outliers"]
+    nx, ny, nz = info["dims"]
     out = dict(info=info)
-    if info["codec"] == ARC_HUFFMAN:
-        nch, nw = info["n_a"], info["n_words"]
-        ob = a16(HDR_BYTES + nb)
-        ow = a16(ob + 4 * nch)
-        oo = a16(ow + 4 * nw)
-        out["len"] = buf[HDR_BYTES:HDR_BYTES + nb].copy()
-        out["bits"] = buf[ob:ob + 4 * nch].view(np.uint32).copy()
-        out["words"] = buf[ow:ow + 4 * nw].view(np.uint32).copy()
+    if info["codec"] in (ARC_HUFFMAN, ARC_RLE_VLE):
+        m = nx * ny * nz if info["codec"] == ARC_HUFFMAN else info["n_a"]
+        L = huffman_layout(m, nb, info["hc"], info["n_words"])
+        out["layout"] = L
+        out["len"] = buf[L["len"]:L["len"] + nb].copy()
+        out["sbits"] = buf[L["sbits"]:L["sbits"] + 2 * L["n_sub"]].view(np.uint16).copy()
+        out["words"] = buf[L["words"]:L["words"] + 4 * info["n_words"]].view(np.uint32).copy()
+        oo = L["end"]
+        if info["codec"] == ARC_RLE_VLE:
+            r = info["n_a"]
+            out["off_rlen"] = oo
+            out["rlen"] = buf[oo:oo + 4 * r].view(np.uint32).copy()
+            oo = _a16(oo + 4 * r)
     elif info["codec"] == ARC_RLE:
         r = info["n_a"]
-        ol = a16(HDR_BYTES + 2 * r)
-        oo = a16(ol + 4 * r)
+        ol = _a16(HDR_BYTES + 2 * r)
+        oo = _a16(ol + 4 * r)
+        out["off_rlen"] = ol
         out["val"] = buf[HDR_BYTES:HDR_BYTES + 2 * r].view(np.uint16).copy()
         out["rlen"] = buf[ol:ol + 4 * r].view(np.uint32).copy()
     else:
         return out
+    out["off_oidx"] = oo
     out["oidx"] = buf[oo:oo + 4 * no].view(np.uint32).copy()
-    ov = a16(oo + 4 * no)
+    ov = _a16(oo + 4 * no)
     out["oval"] = buf[ov:ov + 4 * no].view(np.int32).copy()
     return out
 
@@ -345,13 +396,14 @@ def sections(a: bytes) -> dict:
 def intermediates(x: np.ndarray, eb: float, mode: str = "rel", n_bins: int = 1024, chunk=None,
                   rank: int | None = None) -> dict:
     """Every intermediate of the compression pipeline, step by step."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
+    fp64 = _is64(x)
+    x = np.ascontiguousarray(x, dtype=np.float64 if fp64 else np.float32)
     rank = rank or x.ndim
     mn, mx = value_range(x)
     rng = float(mx) - float(mn)
     M = max(abs(float(mn)), abs(float(mx)))
     eb_abs = eb * rng if mode == "rel" else eb
-    ebx2, inv, e = quant_step(M, eb_abs)
+    ebx2, inv, e = quant_step(M, eb_abs, fp64)
     d = prequant(x, inv)
     delta = lorenzo(d, rank, chunk)
     q, idx, val = postquant(delta, n_bins)

@@ -48,7 +48,7 @@ def _compile(src: str) -> str:
                "-I", ROCM_INCLUDE, "-I", INCLUDE,
                "-c", os.path.join(CSRC, src), "-o", obj]
     else:
-        cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *CFLAGS, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")

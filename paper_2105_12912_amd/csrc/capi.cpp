@@ -164,6 +164,7 @@ struct Geo {
     uint32_t wx, xs, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
     uint32_t grid;  // persistent construction grid (workgroups)
     uint32_t n_seg, range_units, ow_units, n_hch, hwg_units, hdwg_units, n_rt;
+    uint32_t hs, n_sub, hpwg_units;
 };
 
 Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc)
@@ -196,7 +197,10 @@ Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc)
     g.ow_units = outlier_write_units(g.n_seg);
     g.n_hch = cdiv(g.n, hc);
     g.hwg_units = cdiv(g.n_hch, huff_cpw(hc));
-    g.hdwg_units = cdiv(g.n_hch, kBlock);
+    g.hs = std::min(hc, kSubMax);
+    g.n_sub = cdiv(g.n, g.hs);
+    g.hdwg_units = cdiv(g.n_sub, kDecLanes);
+    g.hpwg_units = cdiv(g.n_hch, kBlock);
     g.n_rt = cdiv(g.n, kRleTile);
     return g;
 }
@@ -227,12 +231,13 @@ struct Batch {
     };
     std::vector<Group> groups;
     uint32_t tot_range = 0, tot_seg = 0, tot_ow = 0, tot_hch = 0, tot_hwg = 0, tot_hdwg = 0,
-             tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0, tot_fx = 0;
+             tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0, tot_fx = 0, tot_sub = 0, tot_hpwg = 0;
     uint32_t max_rle_units = 0;
+    bool overflow = false;  // some work-unit total of the batch reached 2^32
     FieldDesc* d_fd = nullptr;
     FieldDyn* d_dyn = nullptr;
     uint32_t *d_seg = nullptr, *d_wcnt = nullptr, *d_rcnt = nullptr, *d_starts = nullptr,
-             *d_tmp = nullptr;
+             *d_tmp = nullptr, *d_soff = nullptr;
     uint8_t* d_tabs = nullptr;
     uint64_t* d_result = nullptr;
     uint64_t ws_bytes = 0;
@@ -262,6 +267,21 @@ uint32_t resident_grid(int rank, bool vec, uint32_t n_bins)
     return g;
 }
 
+// Work-unit totals are summed in 64 bits: a batch whose total in any index
+// space reaches 2^32 cannot be addressed by the 32-bit unit indices of the
+// kernels and is rejected by the caller (Batch::overflow).
+struct Tot {
+    uint64_t v = 0;
+    bool* over;
+    uint32_t add(uint64_t x)
+    {
+        const uint32_t base = (uint32_t)v;
+        v += x;
+        if (v >= 0xFFFFFFFFull) *over = true;
+        return base;
+    }
+};
+
 void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec, uint32_t n_bins)
 {
     const int nf = B.nf;
@@ -273,26 +293,38 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
     });
     B.order = idx;
     B.groups.clear();
+    B.overflow = false;
+    bool* ov = &B.overflow;
+    Tot range{0, ov}, seg{0, ov}, ow{0, ov}, hch{0, ov}, hwg{0, ov}, hdwg{0, ov}, rt{0, ov}, wg{0, ov},
+        sub{0, ov}, hpwg{0, ov};
     for (int k = 0; k < nf; ++k) {
         const Geo& g = geo[idx[k]];
         const bool v = vec[idx[k]];
-        if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v)
+        if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v) {
             B.groups.push_back({g.rank, v, k, 0, 0, 0});
+            wg.v = 0;
+        }
         Batch::Group& G = B.groups.back();
         FieldDesc& d = B.fd[k];
-        d.wg_base = G.wg_tiles;
+        d.wg_base = wg.add(g.wg_tiles);
         d.wg_tiles = g.wg_tiles;
-        G.wg_tiles += g.wg_tiles;
+        G.wg_tiles = (uint32_t)wg.v;
         G.count++;
-        d.range_base = B.tot_range, d.range_units = g.range_units, B.tot_range += g.range_units;
-        d.seg_base = B.tot_seg, d.n_seg = g.n_seg, B.tot_seg += g.n_seg;
-        d.ow_base = B.tot_ow, d.ow_units = g.ow_units, B.tot_ow += g.ow_units;
-        d.hch_base = B.tot_hch, d.n_hch = g.n_hch, B.tot_hch += g.n_hch;
-        d.hwg_base = B.tot_hwg, d.hwg_units = g.hwg_units, B.tot_hwg += g.hwg_units;
-        d.hdwg_base = B.tot_hdwg, d.hdwg_units = g.hdwg_units, B.tot_hdwg += g.hdwg_units;
-        d.rt_base = B.tot_rt, d.n_rt = g.n_rt, B.tot_rt += g.n_rt;
+        d.range_base = range.add(g.range_units), d.range_units = g.range_units;
+        d.seg_base = seg.add(g.n_seg), d.n_seg = g.n_seg;
+        d.ow_base = ow.add(g.ow_units), d.ow_units = g.ow_units;
+        d.hch_base = hch.add(g.n_hch), d.n_hch = g.n_hch;
+        d.hwg_base = hwg.add(g.hwg_units), d.hwg_units = g.hwg_units;
+        d.hdwg_base = hdwg.add(g.hdwg_units), d.hdwg_units = g.hdwg_units;
+        d.hs = g.hs;
+        d.sub_base = sub.add(g.n_sub), d.n_sub = g.n_sub;
+        d.hpwg_base = hpwg.add(g.hpwg_units), d.hpwg_units = g.hpwg_units;
+        d.rt_base = rt.add(g.n_rt), d.n_rt = g.n_rt;
         B.max_rle_units = std::max(B.max_rle_units, cdiv(g.n, kBlock));
     }
+    B.tot_range = (uint32_t)range.v, B.tot_seg = (uint32_t)seg.v, B.tot_ow = (uint32_t)ow.v;
+    B.tot_hch = (uint32_t)hch.v, B.tot_hwg = (uint32_t)hwg.v, B.tot_hdwg = (uint32_t)hdwg.v;
+    B.tot_rt = (uint32_t)rt.v, B.tot_sub = (uint32_t)sub.v, B.tot_hpwg = (uint32_t)hpwg.v;
     for (auto& G : B.groups) {
         uint32_t grid = 0;
         for (int k = G.first; k < G.first + G.count; ++k) grid = std::max(grid, geo[B.order[k]].grid);
@@ -331,7 +363,7 @@ struct CompressIn {
     uint64_t cap;
 };
 
-void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P, uint8_t* ws)
+int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P, uint8_t* ws)
 {
     B.nf = (int)fin.size();
     B.fd.assign(B.nf, FieldDesc{});
@@ -377,6 +409,8 @@ void plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P
         d.hbits = bp.take<uint32_t>(4ull * g.n_hch);
     }
     B.ws_bytes = bp.off;
+    if (B.overflow) return fail(EBC_ERR_DIMS, "batch too large: a work-unit total reaches 2^32");
+    return EBC_OK;
 }
 
 // ------------------------------------------------------------------ timing
@@ -479,11 +513,11 @@ int compress_common(const std::vector<CompressIn>& fin, const ebc_params* p, voi
     }
     if (!d_ws) return fail(EBC_ERR_ARG, "workspace is NULL");
     Batch sizing;
-    plan_compress(sizing, fin, P, nullptr);
+    if (int e_ = plan_compress(sizing, fin, P, nullptr)) return e_;
     if (ws_bytes < sizing.ws_bytes)
         return fail(EBC_ERR_WS_TOO_SMALL, "workspace %llu < required %llu",
                     (unsigned long long)ws_bytes, (unsigned long long)sizing.ws_bytes);
-    plan_compress(B, fin, P, (uint8_t*)d_ws);
+    if (int e_ = plan_compress(B, fin, P, (uint8_t*)d_ws)) return e_;
     return EBC_OK;
 }
 
@@ -505,15 +539,15 @@ void fill_stats(ebc_stats* st, const FieldDyn& d, uint64_t n)
 
 // ------------------------------------------------------------------ decompress plan
 struct Header {
-    int rank, codec, eb_mode;
-    uint32_t n_bins, hc;
+    int rank, codec, eb_mode, dtype;
+    uint32_t n_bins, hc, hs;
     uint64_t dims[3];
     uint32_t chunk[3];
     double eb, eb_abs, ebx2;
-    float cval;
+    double cval;
     uint64_t n_out, n_a, n_words, total;
     uint64_t n;
-    uint64_t off_bits, off_words, off_val, off_rlen, off_oidx, off_oval;
+    uint64_t off_sbits, off_words, off_val, off_rlen, off_oidx, off_oval;
 };
 
 int parse_header(const void* h, uint64_t bytes, Header* H)
@@ -524,8 +558,8 @@ int parse_header(const void* h, uint64_t bytes, Header* H)
     if (memcmp(a, "EBC1", 4) != 0) return fail(EBC_ERR_ARCHIVE, "bad magic");
     uint16_t ver;
     memcpy(&ver, a + 4, 2);
-    if (ver != 1) return fail(EBC_ERR_ARCHIVE, "unsupported version %u", ver);
-    H->rank = a[8], H->codec = a[9], H->eb_mode = a[10];
+    if (ver != 2) return fail(EBC_ERR_ARCHIVE, "unsupported version %u", ver);
+    H->rank = a[8], H->codec = a[9], H->eb_mode = a[10], H->dtype = a[11];
     memcpy(&H->n_bins, a + 12, 4);
     memcpy(H->dims, a + 16, 24);
     memcpy(H->chunk, a + 40, 12);
@@ -533,12 +567,14 @@ int parse_header(const void* h, uint64_t bytes, Header* H)
     memcpy(&H->eb, a + 56, 8);
     memcpy(&H->eb_abs, a + 64, 8);
     memcpy(&H->ebx2, a + 72, 8);
-    memcpy(&H->cval, a + 80, 4);
+    memcpy(&H->cval, a + 80, 8);
     memcpy(&H->n_out, a + 88, 8);
     memcpy(&H->n_a, a + 96, 8);
     memcpy(&H->n_words, a + 104, 8);
     memcpy(&H->total, a + 112, 8);
-    if (H->codec > 2) return fail(EBC_ERR_ARCHIVE, "bad codec byte");
+    memcpy(&H->hs, a + 120, 4);
+    if (H->codec > 3) return fail(EBC_ERR_ARCHIVE, "bad codec byte");
+    if (H->dtype > 1) return fail(EBC_ERR_ARCHIVE, "bad data type byte");
     if (H->rank < 1 || H->rank > 3) return fail(EBC_ERR_ARCHIVE, "bad rank");
     uint64_t n;
     if (check_dims(H->rank, H->dims, &n)) return fail(EBC_ERR_ARCHIVE, "bad dims");
@@ -553,10 +589,22 @@ int parse_header(const void* h, uint64_t bytes, Header* H)
     if (H->codec == EBC_ARC_HUFFMAN) {
         const uint64_t nch = (n + H->hc - 1) / H->hc;
         if (H->n_a != nch) return fail(EBC_ERR_ARCHIVE, "chunk count mismatch");
+        if (H->hs != std::min(H->hc, kSubMax)) return fail(EBC_ERR_ARCHIVE, "bad sub-chunk length");
         if (H->n_words > 2 * n + nch) return fail(EBC_ERR_ARCHIVE, "word count too large");
-        H->off_bits = a16h(kHdr + H->n_bins);
-        H->off_words = a16h(H->off_bits + 4 * nch);
+        const uint64_t nsub = (n + H->hs - 1) / H->hs;
+        H->off_sbits = a16h(kHdr + H->n_bins);
+        H->off_words = a16h(H->off_sbits + 2 * nsub);
         H->off_oidx = a16h(H->off_words + 4 * H->n_words);
+    } else if (H->codec == EBC_ARC_RLE_VLE) {
+        if (H->n_a > n || H->n_a == 0) return fail(EBC_ERR_ARCHIVE, "bad run count");
+        if (H->hs != std::min(H->hc, kSubMax)) return fail(EBC_ERR_ARCHIVE, "bad sub-chunk length");
+        const uint64_t nch = (H->n_a + H->hc - 1) / H->hc;
+        if (H->n_words > 2 * H->n_a + nch) return fail(EBC_ERR_ARCHIVE, "word count too large");
+        const uint64_t nsub = (H->n_a + H->hs - 1) / H->hs;
+        H->off_sbits = a16h(kHdr + H->n_bins);
+        H->off_words = a16h(H->off_sbits + 2 * nsub);
+        H->off_rlen = a16h(H->off_words + 4 * H->n_words);
+        H->off_oidx = a16h(H->off_rlen + 4 * H->n_a);
     } else {
         if (H->n_a > n || H->n_a == 0) return fail(EBC_ERR_ARCHIVE, "bad run count");
         if (H->n_words != 0) return fail(EBC_ERR_ARCHIVE, "RLE archive with Huffman words");
@@ -572,6 +620,8 @@ int parse_header(const void* h, uint64_t bytes, Header* H)
 
 int header_supported(const Header& H)
 {
+    if (H.dtype != 0) return fail(EBC_ERR_UNSUPPORTED, "fp64 archives are not implemented");
+    if (H.codec == EBC_ARC_RLE_VLE) return fail(EBC_ERR_UNSUPPORTED, "RLE+VLE archives are not implemented");
     if (H.codec == EBC_ARC_CONST) return EBC_OK;
     const uint32_t want[3][3] = {{256, 1, 1}, {16, 16, 1}, {8, 8, 8}};
     for (int k = 0; k < 3; ++k)
@@ -590,7 +640,7 @@ struct DecompressIn {
     uint64_t out_elems;
 };
 
-void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
+int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
 {
     B.nf = (int)din.size();
     B.fd.assign(B.nf, FieldDesc{});
@@ -606,8 +656,9 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
     // per-codec unit counts (other codecs get zero units)
-    B.tot_hch = B.tot_hdwg = B.tot_rt = B.tot_runs = B.tot_sc = B.tot_rl = B.tot_fx = 0;
-    B.tot_range = 0;
+    bool* ov = &B.overflow;
+    Tot hch{0, ov}, hdwg{0, ov}, rt{0, ov}, runs{0, ov}, sc{0, ov}, rl{0, ov}, fx{0, ov}, range{0, ov},
+        sub{0, ov}, hpwg{0, ov};
     for (int k = 0; k < B.nf; ++k) {
         const DecompressIn& D = din[B.order[k]];
         const Header& H = D.H;
@@ -616,25 +667,31 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.codec_hdr = H.codec;
         const bool huff = H.codec == EBC_ARC_HUFFMAN, rle = H.codec == EBC_ARC_RLE,
                    cst = H.codec == EBC_ARC_CONST;
-        d.hch_base = B.tot_hch, d.n_hch = huff ? g.n_hch : 0, B.tot_hch += d.n_hch;
-        d.hdwg_base = B.tot_hdwg, d.hdwg_units = huff ? g.hdwg_units : 0, B.tot_hdwg += d.hdwg_units;
-        d.rt_base = B.tot_rt, d.n_rt = rle ? g.n_rt : 0, B.tot_rt += d.n_rt;
-        d.rle_base = B.tot_runs, d.n_runs_hdr = rle ? (uint32_t)H.n_a : 0, B.tot_runs += d.n_runs_hdr;
-        d.rl_base = B.tot_rl, d.rl_units = cdiv(d.n_runs_hdr, kBlock), B.tot_rl += d.rl_units;
-        const uint32_t sc = cst ? 0 : cdiv(H.n_out, kBlock);
-        d.sc_base = B.tot_sc, d.sc_units = sc, B.tot_sc += sc;
+        d.n_hch = huff ? g.n_hch : 0, d.hch_base = hch.add(d.n_hch);
+        d.hdwg_units = huff ? g.hdwg_units : 0, d.hdwg_base = hdwg.add(d.hdwg_units);
+        d.hs = g.hs;
+        d.n_sub = huff ? g.n_sub : 0, d.sub_base = sub.add(d.n_sub);
+        d.hpwg_units = huff ? g.hpwg_units : 0, d.hpwg_base = hpwg.add(d.hpwg_units);
+        d.n_rt = rle ? g.n_rt : 0, d.rt_base = rt.add(d.n_rt);
+        d.n_runs_hdr = rle ? (uint32_t)H.n_a : 0, d.rle_base = runs.add(d.n_runs_hdr);
+        d.rl_units = cdiv(d.n_runs_hdr, kBlock), d.rl_base = rl.add(d.rl_units);
+        d.sc_units = cst ? 0 : cdiv(H.n_out, kBlock), d.sc_base = sc.add(d.sc_units);
         // 3D: at most one fix-up chunk per outlier, a wave each
-        const uint32_t fx = (cst || H.rank != 3) ? 0 : cdiv(H.n_out, kWavesPerBlock);
-        d.fx_base = B.tot_fx, d.fx_units = fx, B.tot_fx += fx;
-        d.range_base = B.tot_range, d.range_units = cst ? g.range_units : 0, B.tot_range += d.range_units;
+        d.fx_units = (cst || H.rank != 3) ? 0 : cdiv(H.n_out, kWavesPerBlock);
+        d.fx_base = fx.add(d.fx_units);
+        d.range_units = cst ? g.range_units : 0, d.range_base = range.add(d.range_units);
         if (cst) {
             // no reconstruction work for a constant field
             d.wg_tiles = 0;
         }
     }
+    B.tot_hch = (uint32_t)hch.v, B.tot_hdwg = (uint32_t)hdwg.v, B.tot_rt = (uint32_t)rt.v;
+    B.tot_runs = (uint32_t)runs.v, B.tot_sc = (uint32_t)sc.v, B.tot_rl = (uint32_t)rl.v;
+    B.tot_fx = (uint32_t)fx.v, B.tot_range = (uint32_t)range.v;
+    B.tot_sub = (uint32_t)sub.v, B.tot_hpwg = (uint32_t)hpwg.v;
     // reconstruct groups: recount WG tiles without constant fields
     for (auto& G : B.groups) {
-        G.wg_tiles = 0;
+        Tot wg{0, ov};
         for (int k = G.first; k < G.first + G.count; ++k) {
             FieldDesc& d = B.fd[k];
             const Geo& g = geo[B.order[k]];
@@ -644,13 +701,14 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
                 recon3_tiles(g, t3);
                 wt = t3[0] * t3[1] * t3[2];
             }
-            d.wg_base = G.wg_tiles;
+            d.wg_base = wg.add(wt);
             d.wg_tiles = wt;
-            G.wg_tiles += wt;
         }
+        G.wg_tiles = (uint32_t)wg.v;
         G.blocks = G.wg_tiles;  // one workgroup per tile
     }
     B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
+    B.d_soff = bp.take<uint32_t>(4ull * (B.tot_sub + 1));
     B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
     B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(std::max(B.tot_hch, B.tot_runs)));
     B.d_tabs = bp.take<uint8_t>(dectab_bytes() * B.nf);
@@ -680,7 +738,8 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.n_words_hdr = H.n_words;
         d.ebx2_hdr = H.ebx2;
         d.cval = H.cval;
-        d.off_bits = H.off_bits, d.off_words = H.off_words, d.off_val = H.off_val;
+        d.dtype = H.dtype;
+        d.off_sbits = H.off_sbits, d.off_words = H.off_words, d.off_val = H.off_val;
         d.off_rlen = H.off_rlen, d.off_oidx = H.off_oidx, d.off_oval = H.off_oval;
         const bool cst = H.codec == EBC_ARC_CONST;
         d.q = bp.take<uint16_t>(cst ? 0 : 2 * g.n);
@@ -691,6 +750,8 @@ void plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws
         d.fixl = bp.take<uint32_t>(r3 ? 4ull * H.n_out : 0);
     }
     B.ws_bytes = bp.off;
+    if (B.overflow) return fail(EBC_ERR_DIMS, "batch too large: a work-unit total reaches 2^32");
+    return EBC_OK;
 }
 
 // Outlier scatter and reconstruction.  The 3D reconstruction reads no
@@ -723,13 +784,13 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     HIP_TRY(launch_dinit(B.d_fd, nf, s));
     T.mark("decode_prep");
     if (B.tot_hch) {
-        HIP_TRY(launch_huff_prep(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, s));
+        HIP_TRY(launch_huff_prep(B.d_fd, nf, B.tot_hpwg, B.d_wcnt, B.d_soff, s));
         HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
         HIP_TRY(launch_words_check(B.d_fd, nf, B.d_wcnt, s));
         T.mark("dectab");
         HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, s));
         T.mark("huffman_decode");
-        HIP_TRY(launch_huff_decode(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, B.d_tabs, dectab_bytes(), s));
+        HIP_TRY(launch_huff_decode(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, B.d_soff, B.d_tabs, dectab_bytes(), s));
     }
     if (B.tot_runs) {
         T.mark("rle_decode");
@@ -797,6 +858,15 @@ int status_of(const FieldDyn& d)
 
 }  // namespace
 
+int ebc::set_error(int status, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return status;
+}
+
 // ====================================================================== ABI
 extern "C" {
 
@@ -863,12 +933,16 @@ int ebc_compress_bound(int rank, const uint64_t dims[3], const ebc_params* p, ui
     st = check_params(p, &P);
     if (st && st != EBC_ERR_UNSUPPORTED) return st;
     const uint32_t hc = p->huff_chunk ? p->huff_chunk : 1024u;
-    const uint64_t nch = (n + hc - 1) / hc;
+    const uint64_t nch = (n + hc - 1) / hc, nsub = (n + std::min(hc, kSubMax) - 1) / std::min(hc, kSubMax);
     uint32_t lb = 0;
     while ((1ull << lb) < p->n_bins) ++lb;
-    const uint64_t huff = a16h(p->n_bins) + a16h(4 * nch) + a16h(4 * ((n * lb + 31) / 32 + nch));
+    // a Huffman stream of N symbols: no more bits than a fixed-length code,
+    // plus one partial word per chunk; RLE+VLE: such a stream over the run
+    // values plus the run lengths
+    const uint64_t huff = a16h(p->n_bins) + a16h(2 * nsub) + a16h(4 * ((n * lb + 31) / 32 + nch));
     const uint64_t rle = a16h(2 * n) + a16h(4 * n);
-    *max_bytes = kHdr + std::max(huff, rle) + a16h(4 * n) + a16h(4 * n);
+    const uint64_t rv = huff + a16h(4 * n);
+    *max_bytes = kHdr + std::max({huff, rle, rv}) + a16h(4 * n) + a16h(4 * n);
     return EBC_OK;
 }
 
@@ -885,7 +959,7 @@ int ebc_compress_workspace_size(int rank, const uint64_t dims[3], const ebc_para
     std::vector<CompressIn> fin(1);
     fin[0] = {(const float*)nullptr, rank, {dims[0], dims[1], dims[2]}, nullptr, 0};
     Batch B;
-    plan_compress(B, fin, P, nullptr);
+    if (int e_ = plan_compress(B, fin, P, nullptr)) return e_;
     *bytes = B.ws_bytes;
     return EBC_OK;
 }
@@ -971,7 +1045,7 @@ int ebc_decompress_workspace_size(const void* h_header, uint64_t header_bytes, u
     if (st) return st;
     din[0].arc = nullptr, din[0].out = nullptr, din[0].size = din[0].H.total, din[0].out_elems = 0;
     Batch B;
-    plan_decompress(B, din, nullptr);
+    if (int e_ = plan_decompress(B, din, nullptr)) return e_;
     *bytes = B.ws_bytes;
     return EBC_OK;
 }
@@ -990,11 +1064,11 @@ static int decompress_impl(const Header& H, const void* d_archive, uint64_t size
     std::vector<DecompressIn> din(1);
     din[0] = {H, d_archive, size, d_out, out_elems};
     Batch sizing;
-    plan_decompress(sizing, din, nullptr);
+    if (int e_ = plan_decompress(sizing, din, nullptr)) return e_;
     if (ws_bytes < sizing.ws_bytes)
         return fail(EBC_ERR_WS_TOO_SMALL, "workspace %llu < required %llu",
                     (unsigned long long)ws_bytes, (unsigned long long)sizing.ws_bytes);
-    plan_decompress(B, din, (uint8_t*)d_ws);
+    if (int e_ = plan_decompress(B, din, (uint8_t*)d_ws)) return e_;
     return enqueue_decompress(B, s, T);
 }
 
@@ -1070,7 +1144,7 @@ int ebc_batch_compress_workspace_size(int n, const ebc_field* fields, const ebc_
                   fields[i].out_cap};
     }
     Batch B;
-    plan_compress(B, fin, P, nullptr);
+    if (int e_ = plan_compress(B, fin, P, nullptr)) return e_;
     *bytes = B.ws_bytes;
     return EBC_OK;
 }
@@ -1156,7 +1230,7 @@ int ebc_batch_decompress_workspace_size(int n, const ebc_archive_ref* refs, uint
     int st = batch_dec_inputs(n, refs, din);
     if (st) return st;
     Batch B;
-    plan_decompress(B, din, nullptr);
+    if (int e_ = plan_decompress(B, din, nullptr)) return e_;
     *bytes = B.ws_bytes;
     return EBC_OK;
 }
@@ -1174,9 +1248,9 @@ static int batch_dec_prepare(int n, const ebc_archive_ref* refs, void* d_ws, uin
         if (D.out_elems < D.H.n) return fail(EBC_ERR_OUT_TOO_SMALL, "output too small");
     }
     Batch sizing;
-    plan_decompress(sizing, din, nullptr);
+    if (int e_ = plan_decompress(sizing, din, nullptr)) return e_;
     if (ws_bytes < sizing.ws_bytes) return fail(EBC_ERR_WS_TOO_SMALL, "workspace too small");
-    plan_decompress(B, din, (uint8_t*)d_ws);
+    if (int e_ = plan_decompress(B, din, (uint8_t*)d_ws)) return e_;
     Timer T(nullptr, s);
     return enqueue_decompress(B, s, T);
 }
@@ -1285,10 +1359,10 @@ int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int
     std::vector<DecompressIn> din(1);
     din[0] = {H, (const void*)o_base, ~0ull, d_out, H.n};
     Batch sizing;
-    plan_decompress(sizing, din, nullptr);
+    if (int e_ = plan_decompress(sizing, din, nullptr)) return e_;
     if (ws_bytes < sizing.ws_bytes) return fail(EBC_ERR_WS_TOO_SMALL, "workspace too small");
     Batch B;
-    plan_decompress(B, din, (uint8_t*)d_ws);
+    if (int e_ = plan_decompress(B, din, (uint8_t*)d_ws)) return e_;
     FieldDesc& d = B.fd[0];
     HIP_TRY(hipMemcpyAsync(d.q, d_q, 2 * H.n, hipMemcpyDeviceToDevice, s));
     d.n_hch = 0, d.hdwg_units = 0;  // no entropy decoding

@@ -9,6 +9,9 @@
 
 namespace ebc {
 
+// Records a failure detail for ebc_last_error() (calling thread) and returns status.
+int set_error(int status, const char* fmt, ...);
+
 constexpr int kDescPerLaunch = 8;
 struct DescBlob {
     int first;
@@ -40,9 +43,11 @@ hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t
 hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_t hc,
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s);
 hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, hipStream_t s);
-hipError_t launch_huff_prep(const FieldDesc* F, int nf, uint32_t units, uint32_t* wcnt, hipStream_t s);
+hipError_t launch_huff_prep(const FieldDesc* F, int nf, uint32_t units, uint32_t* wcnt, uint32_t* soff,
+                            hipStream_t s);
 hipError_t launch_huff_decode(const FieldDesc* F, int nf, uint32_t units, const uint32_t* woff,
-                              const uint8_t* tabs, size_t tab_stride, hipStream_t s);
+                              const uint32_t* soff, const uint8_t* tabs, size_t tab_stride,
+                              hipStream_t s);
 
 // RLE
 hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t* rcnt, hipStream_t s);

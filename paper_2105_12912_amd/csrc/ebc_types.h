@@ -35,6 +35,8 @@ constexpr int kLutBits = 12;                // Huffman decode table width (bits 
 constexpr int kMaxDecodeLen = 60;          // longest code the decoder accepts (N < 2^32 gives <= 46)
 constexpr uint32_t kL2Size = 2048;         // second-level decode table entries
 constexpr uint32_t kL2MaxBits = 8;         // bits a second-level table resolves at most
+constexpr uint32_t kSubMax = 256;          // Huffman sub-chunk symbols (hs = min(hc, kSubMax))
+constexpr uint32_t kDecLanes = 768;        // decode workgroup: one lane per sub-chunk
 
 enum : int32_t { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2 };
 enum : int32_t { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2 };
@@ -60,7 +62,7 @@ struct FieldDyn {
     uint64_t n_words;
     uint64_t huff_bits;
     uint64_t total;
-    uint64_t off_bits, off_words, off_rlen, off_oidx, off_oval;
+    uint64_t off_sbits, off_words, off_rlen, off_oidx, off_oval;
     uint32_t max_len;
     uint32_t n_used;  // symbols with a non-zero count
     uint64_t zero_count;
@@ -113,8 +115,11 @@ struct FieldDesc {
     uint32_t n_seg, seg_base;          // outlier segments: count-array entries
     uint32_t ow_units, ow_base;        // outlier write: 1024 segments per WG
     uint32_t n_hch, hch_base;          // Huffman chunks: word-count array entries
+    uint32_t hs;                       // Huffman sub-chunk symbols: min(hc, 256)
+    uint32_t n_sub, sub_base;          // Huffman sub-chunks: in-chunk start offsets
     uint32_t hwg_units, hwg_base;      // Huffman encode: huff_cpw(hc) chunks per WG
-    uint32_t hdwg_units, hdwg_base;    // Huffman decode: 256 chunks per WG
+    uint32_t hdwg_units, hdwg_base;    // Huffman decode: kDecLanes sub-chunks per WG
+    uint32_t hpwg_units, hpwg_base;    // Huffman decode prologue: kBlock chunks per WG
     uint32_t n_rt, rt_base;            // RLE tiles of kRleTile elements (count array / WG)
     uint32_t n_runs_hdr, rle_base;     // decompress: runs in the archive (start array entries)
     uint32_t sc_units, sc_base;        // decompress outlier scatter: 256 outliers per WG
@@ -124,9 +129,10 @@ struct FieldDesc {
     uint64_t n_out_hdr;
     uint64_t n_words_hdr;
     double ebx2_hdr;
-    float cval;
+    double cval;
     int32_t codec_hdr;
-    uint64_t off_bits, off_words, off_val, off_rlen, off_oidx, off_oval;
+    int32_t dtype;
+    uint64_t off_sbits, off_words, off_val, off_rlen, off_oidx, off_oval;
 };
 
 // Canonical Huffman decoder tables of one field (built by k_dectab).

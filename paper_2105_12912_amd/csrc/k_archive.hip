@@ -1,8 +1,11 @@
 // k_archive.hip -- archive layout, header and padding, descriptor upload.
 //
-// Archive format v1 (little-endian, 128-byte header, every section starts on
+// Archive format v2 (little-endian, 128-byte header, every section starts on
 // a 16-byte boundary, padding is zero):
-//   Huffman: u8 len[n_bins] | u32 bits[n_chunks] | u32 words[n_words]
+//   Huffman: u8 len[n_bins] | u16 sbits[n_sub] | u32 words[n_words]
+//            (sbits: bit count of every sub-chunk of hs = min(hc, 256)
+//            symbols; chunks of hc symbols start on a word, their sub-chunks
+//            follow each other without padding)
 //   RLE:     u16 val[n_runs] | u32 len[n_runs]
 //   both:    u32 outlier_index[n_out] | i32 outlier_delta[n_out]
 // The paper leaves the container unspecified; the header records everything
@@ -33,8 +36,8 @@ __global__ void k_layout(const FieldDesc* __restrict__ F, int nf, const uint32_t
         const uint64_t nw = woff[fd.hch_base + fd.n_hch] - woff[fd.hch_base];
         dy->n_words = nw;
         dy->n_runs = 0;
-        dy->off_bits = align16(kHdr + fd.n_bins);
-        dy->off_words = align16(dy->off_bits + 4ull * fd.n_hch);
+        dy->off_sbits = align16(kHdr + fd.n_bins);
+        dy->off_words = align16(dy->off_sbits + 2ull * fd.n_sub);
         off_o = align16(dy->off_words + 4ull * nw);
     } else {
         const uint64_t R = roff[fd.rt_base + fd.n_rt] - roff[fd.rt_base];
@@ -69,8 +72,9 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
     __syncthreads();
     if (l == 0) {
         h[0] = 0x31434245u;  // "EBC1"
-        h[1] = 1u;           // version 1, flags 0
-        h[2] = (uint32_t)fd.rank | ((uint32_t)dy->codec << 8) | ((uint32_t)fd.eb_mode << 16);
+        h[1] = 2u;           // version 2, flags 0
+        h[2] = (uint32_t)fd.rank | ((uint32_t)dy->codec << 8) | ((uint32_t)fd.eb_mode << 16) |
+               ((uint32_t)fd.dtype << 24);
         h[3] = fd.n_bins;
         const uint64_t dims[3] = {fd.nx, fd.ny, fd.nz};
         for (int k = 0; k < 3; ++k) {
@@ -88,8 +92,10 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
             h[14 + 2 * k] = (uint32_t)b;
             h[15 + 2 * k] = (uint32_t)(b >> 32);
         }
-        h[20] = dy->codec == ARC_CONST ? __float_as_uint(dy->mn) : 0u;
-        h[21] = 0;
+        // constant value as f64 (exact for an fp32 field)
+        const uint64_t cb = dy->codec == ARC_CONST ? (uint64_t)__double_as_longlong((double)dy->mn) : 0ull;
+        h[20] = (uint32_t)cb;
+        h[21] = (uint32_t)(cb >> 32);
         const uint64_t na = dy->codec == ARC_HUFFMAN ? (uint64_t)fd.n_hch : dy->n_runs;
         const uint64_t v[4] = {dy->codec == ARC_CONST ? 0ull : dy->n_out,
                                dy->codec == ARC_CONST ? 0ull : na, dy->n_words, dy->total};
@@ -97,6 +103,8 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
             h[22 + 2 * k] = (uint32_t)v[k];
             h[23 + 2 * k] = (uint32_t)(v[k] >> 32);
         }
+        h[30] = dy->codec == ARC_HUFFMAN ? fd.hs : 0u;
+        h[31] = 0;
     }
     __syncthreads();
     if (l < 32) ((EBC_G uint32_t*)a)[l] = h[l];
@@ -105,8 +113,8 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
     if (dy->codec == ARC_HUFFMAN) {
 #pragma unroll 8
         for (uint32_t s = l; s < fd.n_bins; s += kWave) a[kHdr + s] = fd.len[s];
-        zero_gap(a, kHdr + fd.n_bins, dy->off_bits, l);
-        zero_gap(a, dy->off_bits + 4ull * fd.n_hch, dy->off_words, l);
+        zero_gap(a, kHdr + fd.n_bins, dy->off_sbits, l);
+        zero_gap(a, dy->off_sbits + 2ull * fd.n_sub, dy->off_words, l);
         zero_gap(a, dy->off_words + 4ull * dy->n_words, dy->off_oidx, l);
     } else {
         zero_gap(a, kHdr + 2ull * dy->n_runs, dy->off_rlen, l);

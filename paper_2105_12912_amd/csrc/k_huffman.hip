@@ -266,12 +266,14 @@ struct WriteProc {
             lmax = max(lmax, L);
         }
         for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
-        uint32_t mid = 0;
+        uint32_t sb = 0;
         if (live) {
-            const uint32_t b0 = wave_incl_scan_u32(mybits) - mybits;
-            // lane 32 starts at symbol hc/2: the chunk's midpoint bit offset
-            // (its bit count when the chunk is shorter)
-            mid = (uint32_t)__shfl((int)b0, 32);
+            const uint32_t incl = wave_incl_scan_u32(mybits);
+            const uint32_t b0 = incl - mybits;
+            // bit count of the sub-chunk that starts at this lane (lanes_per_sub
+            // lanes of S symbols each): the scan at its last lane minus b0
+            constexpr uint32_t kLps = kSubMax / S < 64 ? kSubMax / S : 64u;
+            sb = (uint32_t)__shfl((int)incl, (int)min<uint32_t>(lane_id() + kLps - 1, 63)) - b0;
             uint32_t w = b0 >> 5, nacc = b0 & 31;
             uint64_t acc = 0;
             if (!__any(lmax > 32)) {
@@ -302,10 +304,13 @@ struct WriteProc {
             const uint32_t wo = wk[fd.hch_base + u.c] - wk[fd.hch_base];
             EBC_G uint32_t* dst = (EBC_G uint32_t*)(arc + dy->off_words) + wo;
             for (uint32_t i = lane_id(); i < nw; i += kWave) dst[i] = wbuf[i];
-            // chunk entry: bit count, and for hc <= 1024 the midpoint in the
-            // high half (counts stay below 2^16 there)
-            if (lane_id() == 0)
-                ((EBC_G uint32_t*)(arc + dy->off_bits))[u.c] = hc <= 1024 ? cbits | (mid << 16) : cbits;
+            // sub-chunk bit counts (u16): one per kSubMax symbols of the
+            // chunk, or one for the whole chunk when it is shorter
+            constexpr uint32_t kLps = kSubMax / S < 64 ? kSubMax / S : 64u;
+            const uint32_t hs = fd.hs;
+            const uint64_t sub = (uint64_t)u.c * (hc / hs) + lane_id() / kLps;
+            if (lane_id() % kLps == 0 && lo < fd.n && sub < fd.n_sub)
+                ((EBC_G uint16_t*)(arc + dy->off_sbits))[sub] = (uint16_t)sb;
         }
     }
 };
@@ -322,13 +327,12 @@ __global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restri
 
 // ------------------------------------------------------------- decoding
 
-
 __device__ __forceinline__ uint32_t word_at(const EBC_G uint32_t* __restrict__ w, uint32_t nw, uint32_t i)
 {
     return i < nw ? w[i] : 0u;
 }
 
-// 64 stream bits starting at bit `pos` (zero beyond the chunk's words)
+// 64 stream bits starting at bit `pos` (zero beyond the lane's words)
 __device__ __forceinline__ uint64_t window_at(const EBC_G uint32_t* __restrict__ w, uint32_t nw,
                                               uint32_t pos)
 {
@@ -338,30 +342,27 @@ __device__ __forceinline__ uint64_t window_at(const EBC_G uint32_t* __restrict__
     return a;
 }
 
-// Per-lane ring of a stream's 32-bit words in LDS, in two halves.  The next
-// half (16-byte blocks) is always in flight in registers: at a wave-uniform
-// refill point, every kRefillEvery iterations, a lane whose reader has entered
-// the newer half writes the loaded half over the older one and issues the
-// loads of the following one.  A load therefore has a whole refill period to
-// land before it is waited for, and bit top-ups read LDS only.  The decode
-// loop consumes at most one word per iteration (codewords longer than 32 bits
-// leave it), so between two refill points a reader advances at most
-// kRefillEvery <= kHalfWords words and never leaves the ring.
-constexpr uint32_t kRingWords = 16;
+// Per-lane ring of a stream's 32-bit words in LDS, in two halves of one
+// 16-byte block each.  The next block is always in flight in registers: at a
+// wave-uniform refill point, every kRefillEvery steps, a lane whose reader
+// has entered the newer half writes the loaded block over the older half and
+// issues the load of the following one, so a load has a whole refill period
+// to land and bit top-ups read LDS only.  A step takes at most one word, so
+// between two refill points a reader advances at most kRefillEvery <=
+// kHalfWords words and never leaves the ring.
+constexpr uint32_t kRingWords = 8;
 constexpr uint32_t kHalfWords = kRingWords / 2;
-constexpr uint32_t kHalfBlocks = kHalfWords / 4;
 constexpr uint32_t kRingStride = kRingWords + 1;  // odd stride: no bank conflicts across lanes
-constexpr uint32_t kRefillEvery = 8;              // iterations (a power of two, <= kHalfWords)
+constexpr uint32_t kRefillEvery = 4;              // steps between refill points (<= kHalfWords)
 static_assert(kRefillEvery <= kHalfWords, "a reader must not outrun the ring between refills");
 
 struct WordRing {
-    uint32_t* ring;                        // this lane's slots in LDS
-    const EBC_G uint4* __restrict__ blk;   // aligned 16-byte blocks of the stream
-    const EBC_G uint32_t* __restrict__ words;
-    uint32_t nw, o, nblk;  // words, offset of word 0 inside block 0, blocks
-    uint32_t rd;           // next stream word to hand out
-    uint32_t wr;           // block-coordinate words [wr - kRingWords, wr) are in the ring
-    uint4 p[kHalfBlocks];  // blocks wr/4 .. wr/4 + kHalfBlocks - 1, in flight
+    uint32_t* ring;                       // this lane's slots in LDS
+    const EBC_G uint4* __restrict__ blk;  // aligned 16-byte blocks of the stream
+    uint32_t o, nblk;  // offset of the lane's word 0 inside block 0, blocks
+    uint32_t rd;       // next stream word to hand out
+    uint32_t wr;       // block-coordinate words [wr - kRingWords, wr) are in the ring
+    uint4 p;           // block wr / 4, in flight
     __device__ __forceinline__ uint4 fetch(uint32_t j) const
     {
         if (j < nblk) {
@@ -377,71 +378,27 @@ struct WordRing {
     {
         d[0] = v.x, d[1] = v.y, d[2] = v.z, d[3] = v.w;
     }
-    __device__ __forceinline__ void init(uint32_t* r, const EBC_G uint32_t* __restrict__ w, uint32_t n)
+    __device__ __forceinline__ void init(uint32_t* r, const EBC_G uint32_t* __restrict__ w, uint32_t nw)
     {
         ring = r;
-        words = w;
-        nw = n;
         const uintptr_t a = (uintptr_t)w;
         o = (uint32_t)((a & 15u) >> 2);
         blk = (const EBC_G uint4*)(a & ~(uintptr_t)15u);
         nblk = (o + nw + 3) / 4;
-#pragma unroll
-        for (uint32_t j = 0; j < kRingWords / 4; ++j) put(ring + 4 * j, fetch(j));
+        put(ring, fetch(0));
+        put(ring + 4, fetch(1));
         wr = kRingWords;
-#pragma unroll
-        for (uint32_t k = 0; k < kHalfBlocks; ++k) p[k] = fetch(kRingWords / 4 + k);
+        p = fetch(2);
         rd = 0;
     }
     // wave-uniform refill point
     __device__ __forceinline__ void refill()
     {
         if (wr < 4 * nblk && rd + o >= wr - kHalfWords) {
-            uint32_t* d = ring + (wr % kRingWords);
-#pragma unroll
-            for (uint32_t k = 0; k < kHalfBlocks; ++k) put(d + 4 * k, p[k]);
+            put(ring + (wr % kRingWords), p);
             wr += kHalfWords;
-            const uint32_t j = wr / 4;
-#pragma unroll
-            for (uint32_t k = 0; k < kHalfBlocks; ++k) p[k] = fetch(j + k);
+            p = fetch(wr / 4);
         }
-    }
-};
-
-// Output accumulator: up to 7 pending 16-bit symbols in a0/a1 plus overflow
-// in a2; appending up to three symbols is branch-free, and every full group
-// of 8 leaves as one aligned 16-byte store (chunks start at multiples of 8).
-struct SymAcc {
-    uint64_t a0 = 0, a1 = 0, a2 = 0;
-    uint32_t cnt = 0, base = 0;
-    __device__ __forceinline__ void append(EBC_G uint16_t* __restrict__ out, uint64_t syms, uint32_t n)
-    {
-        const uint32_t s = 16 * cnt;  // 0..112
-        const uint32_t s0 = s & 63;
-        const uint64_t lo = syms << s0;
-        const uint64_t hi = s0 ? syms >> (64 - s0) : 0ull;
-        if (s < 64) {
-            a0 |= lo;
-            a1 |= hi;
-        } else {
-            a1 |= lo;
-            a2 |= hi;
-        }
-        cnt += n;
-        if (cnt >= 8) {
-            *(EBC_G uint4*)(out + base) =
-                make_uint4((uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32));
-            base += 8;
-            cnt -= 8;
-            a0 = a2;
-            a1 = 0;
-            a2 = 0;
-        }
-    }
-    __device__ __forceinline__ void flush(EBC_G uint16_t* __restrict__ out)
-    {
-        for (uint32_t k = 0; k < cnt; ++k)
-            out[base + k] = (uint16_t)((k < 4 ? a0 >> (16 * k) : a1 >> (16 * (k - 4))) & 0xFFFF);
     }
 };
 
@@ -470,30 +427,54 @@ struct LongCode {
     }
 };
 
-// Two lanes per chunk: the chunk entry carries the bit offset of the chunk's
-// middle symbol (hc <= 1024), so lane 0 of a pair decodes the first half and
-// lane 1 the second half from that offset; lane 0 must end exactly there.
-constexpr uint32_t kDecBlock = 2 * kBlock;
+// Output staging: each lane collects its decoded symbols in an LDS row and
+// the wave moves them to HBM in blocks of kFlush symbols per lane.  A block
+// leaves when every lane still decoding holds one; the copy is transposed
+// (four consecutive threads write one lane's 64-byte block), so a store
+// instruction writes sixteen whole 64-byte segments.  A lane that runs
+// kCap - 3 symbols ahead of its last flush waits (its steps are empty)
+// until the slower lanes have caught up, which never delays the wave: the
+// waiting lane is ahead of the slowest one.
+constexpr uint32_t kFlush = 32;
+constexpr uint32_t kCap = 46;                     // symbols a row holds; a step needs 3 free slots
+constexpr uint32_t kStageWords = 25;              // row stride (odd): kCap + 3 slots and more
+constexpr uint32_t kCheckEvery = 4;               // steps between flush checks
+static_assert(2 * kStageWords >= kCap + 3, "the three slots of a step stay inside the row");
+static_assert(kCap - 2 > kFlush, "a waiting lane always holds a whole block");
+static_assert(kRefillEvery == kCheckEvery, "refill and flush checks share the step loop");
 
-__global__ __launch_bounds__(kDecBlock) __attribute__((amdgpu_waves_per_eu(4)))
-void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ woff,
-                   const uint8_t* __restrict__ tabs, size_t tab_stride)
+// One lane per sub-chunk (hs = min(hc, 256) symbols, its bit count and its
+// start from the archive's sub-chunk counts), kDecLanes lanes per workgroup.
+// The main loop runs passes of kCheckEvery steps behind one refill point and
+// one flush check.  A step tops the bit buffer up to at least 32 bits
+// (branch-free, with the next stream word read from the ring one step
+// ahead), takes one kLutBits table entry (up to three codewords) and writes
+// its three symbol slots into the lane's row; only the decoded ones count.
+// Codewords longer than the table go through a second-level table or the
+// canonical limit test; longer than 32 bits, the lane leaves for an exact
+// path that reads windows straight from the stream.
+__global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __restrict__ F, int nf,
+                                                          const uint32_t* __restrict__ woff,
+                                                          const uint32_t* __restrict__ soff,
+                                                          const uint8_t* __restrict__ tabs,
+                                                          size_t tab_stride)
 {
     __shared__ uint64_t lut[1u << kLutBits];
     __shared__ uint32_t l2s[kL2Size];
     __shared__ uint64_t s_first[65];
     __shared__ uint64_t s_endv[65];
     __shared__ uint32_t s_off[65];
-    __shared__ uint32_t s_ring[kDecBlock * kRingStride];
+    __shared__ uint32_t s_ring[kDecLanes * kRingStride];
+    __shared__ uint32_t s_stage[kDecLanes * kStageWords];
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
     const DecTab* __restrict__ T = (const DecTab*)(tabs + (size_t)f * tab_stride);
-    for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kDecBlock) lut[i] = T->lut[i];
+    for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kDecLanes) lut[i] = T->lut[i];
     const uint32_t l2k = T->l2k, l2n = T->l2n;
-    for (uint32_t i = threadIdx.x; i < l2n; i += kDecBlock) l2s[i] = T->l2[i];
+    for (uint32_t i = threadIdx.x; i < l2n; i += kDecLanes) l2s[i] = T->l2[i];
     if (threadIdx.x < 65) {
         s_first[threadIdx.x] = T->first[threadIdx.x];
         s_endv[threadIdx.x] = T->endv[threadIdx.x];
@@ -501,38 +482,32 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
     }
     const uint32_t maxl = T->max_len;
     __syncthreads();
-    const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x / 2;
-    const uint32_t half = threadIdx.x & 1;
-    if (c >= fd.n_hch) return;
-    const uint32_t hc = fd.hc;
-    const bool split = hc <= 1024;
+    const uint32_t lane = lane_id();
+    const uint32_t sub0 = (t - fd.hdwg_base) * kDecLanes + (threadIdx.x & ~(uint32_t)(kWave - 1));
+    if (sub0 >= fd.n_sub) return;  // whole wave past the field's sub-chunks
+    const uint32_t sub = sub0 + lane;
+    const bool live = sub < fd.n_sub;
+    const uint32_t hs = fd.hs, per = fd.hc / hs;
+    const uint32_t c = live ? sub / per : 0;
     const EBC_G uint8_t* arc = fd.arc;
-    const uint32_t ent = ((const EBC_G uint32_t*)(arc + fd.off_bits))[c];
-    const uint32_t nbits = split ? ent & 0xFFFFu : ent;
-    const uint32_t mid = split ? ent >> 16 : nbits;
-    const uint32_t nw = (nbits + 31) / 32;
-    const uint32_t wo = woff[fd.hch_base + c] - woff[fd.hch_base];
-    const uint64_t lo = (uint64_t)c * hc;
-    const uint32_t nsym = (uint32_t)min<uint64_t>(hc, fd.n - lo);
-    if ((uint64_t)wo + nw > fd.n_words_hdr || mid > nbits || (split && nsym <= hc / 2 && mid != nbits)) {
-        atomicMin(&dy->status, ST_ERR_ARCHIVE);
-        return;
-    }
-    // this lane's symbols [s0, s1) start at chunk bit b0
-    uint32_t s0 = 0, s1 = nsym, b0 = 0;
-    if (split) {
-        if (half == 0) s1 = min(hc / 2, nsym);
-        else s0 = min(hc / 2, nsym), b0 = mid;
-    } else if (half) {
-        return;
-    }
-    const uint32_t want = s1 - s0;
-    if (want == 0) return;
-    const uint32_t w0 = b0 >> 5;
-    const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + wo + w0;
-    const uint32_t nwl = nw - w0;
-    EBC_G uint16_t* __restrict__ out = fd.q + lo + s0;
+    const uint32_t nbits = live ? ((const EBC_G uint16_t*)(arc + fd.off_sbits))[sub] : 0u;
+    // start bit of the sub-chunk inside the field's word stream
+    const uint64_t b0 = live ? (uint64_t)(woff[fd.hch_base + c] - woff[fd.hch_base]) * 32 +
+                                   soff[fd.sub_base + sub]
+                             : 0ull;
+    const uint64_t lo = (uint64_t)sub * hs;
+    const uint32_t want = live ? (uint32_t)min<uint64_t>(hs, fd.n - lo) : 0u;
+    const uint32_t w0 = (uint32_t)(b0 >> 5);
+    const uint32_t skip = (uint32_t)(b0 & 31);
+    const uint32_t nwl = live ? (skip + nbits + 31) / 32 : 0u;  // words the lane may read
+    // the chunk words were checked against the archive's word count, and a
+    // sub-chunk ends inside its chunk by construction of the offsets
+    const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + w0;
+    EBC_G uint16_t* __restrict__ out = fd.q + lo;
     const LongCode lc{maxl, s_endv, s_first, s_off, T->perm};
+    uint32_t* row = s_stage + threadIdx.x * kStageWords;
+    uint16_t* row16 = (uint16_t*)row;
+    const uint32_t* wave_rows = s_stage + (threadIdx.x - lane) * kStageWords;
 
     WordRing wr;
     wr.init(s_ring + threadIdx.x * kRingStride, words, nwl);
@@ -540,25 +515,16 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
     ++wr.rd;
     buf |= wr.peek();
     ++wr.rd;
-    // positions below are relative to word w0 of the chunk
-    const uint32_t skip = b0 & 31;
     buf <<= skip;
-    uint32_t valid = 64 - skip, pos = skip, j = 0;
-    bool bad = false, slow = false;
-    SymAcc acc;
-    // Main loop: passes of kRefillEvery steps, each pass behind one refill
-    // point; the wave leaves when none of its lanes is still in the fast path.
-    // A step tops the buffer up to at least 32 bits (branch-free, with the
-    // next stream word already read from the ring one step ahead) and takes
-    // one table entry: up to three codewords, fewer at the end of the lane's
-    // symbols.  A lane out of the fast path (done, or moved to the exact path
-    // by a codeword longer than 32 bits) takes steps of zero codewords and
-    // zero bits, which change neither its position nor its output.
+    uint32_t valid = 64 - skip;
+    uint32_t j = 0, sp = 0, flushed = 0;
+    bool slow = false;
+    bool act = want > 0;
     uint32_t nxt = wr.peek();
-    bool act = true;
     while (__any(act)) {
         wr.refill();
-        for (uint32_t u = 0; u < kRefillEvery; ++u) {
+#pragma unroll
+        for (uint32_t u = 0; u < kCheckEvery; ++u) {
             {
                 const bool need = valid < 32;
                 buf |= need ? ((uint64_t)nxt << ((32u - valid) & 63u)) : 0ull;
@@ -570,7 +536,7 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
             const uint32_t eh = (uint32_t)(e >> 32);
             uint32_t n = (eh >> 16) & 3u;
             uint32_t tl = (eh >> 18) & 63u;
-            uint64_t syms = e & 0xFFFFFFFFFFFFull;
+            uint32_t s01 = (uint32_t)e, s2 = eh & 0xFFFFu;
             if (act && n == 0) {
                 // second level, then the canonical search for longer codewords
                 uint32_t sym = 0, L = 0;
@@ -587,26 +553,54 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
                 }
                 n = 1;
                 tl = L;
-                syms = sym;
+                s01 = sym;
             }
-            // the lane's last symbols take only the leading codewords; a lane
-            // out of the fast path takes none
-            const uint32_t left = act ? want - j : 0u;
-            if (n > left) {
-                tl = left == 0 ? 0u : ((eh >> 24) & 15u) + (left == 2 ? eh >> 28 : 0u);
-                syms &= left == 0 ? 0ull : (left == 1 ? 0xFFFFull : 0xFFFFFFFFull);
+            // three symbol slots; only the decoded ones are kept (sp <= kCap)
+            row16[sp] = (uint16_t)s01;
+            row16[sp + 1] = (uint16_t)(s01 >> 16);
+            row16[sp + 2] = (uint16_t)s2;
+            const uint32_t left = want - j;
+            if (act && n > left) {
+                // the lane's last symbols take only the leading codewords
+                tl = ((eh >> 24) & 15u) + (left == 2 ? eh >> 28 : 0u);
                 n = left;
             }
-            acc.append(out, syms, n);
+            const bool go = act && sp + 3 <= kCap;
+            n = go ? n : 0u;
+            tl = go ? tl : 0u;
             j += n;
-            pos += tl;
+            sp += n;
             buf <<= tl;
             valid -= tl;
             act = act && j < want;
         }
+        // a block of kFlush symbols leaves when every lane still decoding has one
+        if (__all(sp >= kFlush || !act)) {
+#pragma unroll
+            for (uint32_t k = 0; k < 4; ++k) {
+                const uint32_t piece = k * kWave + lane;
+                const uint32_t L = piece >> 2, part = piece & 3;
+                const uint32_t spL = (uint32_t)__shfl((int)sp, (int)L);
+                const uint32_t flL = (uint32_t)__shfl((int)flushed, (int)L);
+                if (spL >= kFlush) {
+                    const uint32_t* src = wave_rows + L * kStageWords + part * 4;
+                    const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
+                    *(EBC_G uint4*)(fd.q + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
+                }
+            }
+            if (sp >= kFlush) {
+                // the symbols past the block move to the front of the row
+#pragma unroll
+                for (uint32_t w = 0; w < kStageWords - kFlush / 2; ++w) row[w] = row[kFlush / 2 + w];
+                sp -= kFlush;
+                flushed += kFlush;
+            }
+        }
     }
     // exact path, one codeword at a time from a window read straight from the
     // stream (lanes that met a codeword longer than 32 bits)
+    bool bad = false;
+    uint32_t pos = 32 * wr.rd - valid;  // bits consumed, counted from word w0
     while (slow && j < want) {
         const uint64_t w = window_at(words, nwl, pos);
         const uint64_t e = lut[(uint32_t)(w >> (64 - kLutBits))];
@@ -626,30 +620,50 @@ void k_huff_decode(const FieldDesc* __restrict__ F, int nf, const uint32_t* __re
                 break;
             }
         }
-        acc.append(out, sym, 1);
-        j += 1;
+        row16[sp++] = (uint16_t)sym;
+        ++j;
         pos += L;
+        if (sp >= kCap) {
+            // a full row: its leading block goes straight to HBM
+            for (uint32_t k = 0; k < kFlush; ++k) out[flushed + k] = row16[k];
+            for (uint32_t w = 0; w < kStageWords - kFlush / 2; ++w) row[w] = row[kFlush / 2 + w];
+            sp -= kFlush;
+            flushed += kFlush;
+        }
     }
-    if (!bad) acc.flush(out);
-    // the first half must end exactly at the midpoint, the second within the chunk
-    const uint32_t end = w0 * 32 + pos;
-    if (bad || end > nbits || (split && half == 0 && nsym > hc / 2 && end != mid))
-        atomicMin(&dy->status, ST_ERR_ARCHIVE);
+    if (!bad && live) {
+        // what is left in the row: whole 16-byte groups, then single symbols
+        uint32_t k = 0;
+        for (; k + 8 <= sp; k += 8)
+            *(EBC_G uint4*)(out + flushed + k) = make_uint4(row[k / 2], row[k / 2 + 1], row[k / 2 + 2],
+                                                             row[k / 2 + 3]);
+        for (; k < sp; ++k) out[flushed + k] = row16[k];
+    }
+    // the sub-chunk must take exactly its stored bit count
+    if (live && (bad || pos != skip + nbits)) atomicMin(&dy->status, ST_ERR_ARCHIVE);
 }
 
-// Huffman decompression prologue: word counts of every chunk into the
-// batch-wide array (scanned next into word offsets).
+// Huffman decompression prologue, one thread per chunk: the in-chunk start
+// bit of each of its sub-chunks (the running sum of the stored sub-chunk bit
+// counts) and the chunk's word count (scanned next into word offsets).
 __global__ __launch_bounds__(kBlock) void k_huff_prep(const FieldDesc* __restrict__ F, int nf,
-                                                      uint32_t* __restrict__ wcnt)
+                                                      uint32_t* __restrict__ wcnt,
+                                                      uint32_t* __restrict__ soff)
 {
     const uint32_t t = blockIdx.x;
-    const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
+    const int f = find_field<&FieldDesc::hpwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    const uint32_t c = (t - fd.hdwg_base) * kBlock + threadIdx.x;
+    const uint32_t c = (t - fd.hpwg_base) * kBlock + threadIdx.x;
     if (fd.dyn->codec != ARC_HUFFMAN || c >= fd.n_hch) return;
-    const uint32_t ent = ((const EBC_G uint32_t*)(fd.arc + fd.off_bits))[c];
-    const uint32_t nbits = fd.hc <= 1024 ? ent & 0xFFFFu : ent;
-    wcnt[fd.hch_base + c] = (nbits + 31) / 32;
+    const uint32_t per = fd.hc / fd.hs;
+    const uint32_t s0 = c * per, s1 = min(s0 + per, fd.n_sub);
+    const EBC_G uint16_t* sb = (const EBC_G uint16_t*)(fd.arc + fd.off_sbits);
+    uint32_t run = 0;
+    for (uint32_t k = s0; k < s1; ++k) {
+        soff[fd.sub_base + k] = run;
+        run += sb[k];
+    }
+    wcnt[fd.hch_base + c] = (run + 31) / 32;
 }
 
 #define EBC_HC_DISPATCH(KERNEL, ...)                                                        \
@@ -702,18 +716,21 @@ hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_
     return hipGetLastError();
 }
 
-hipError_t launch_huff_prep(const FieldDesc* F, int nf, uint32_t units, uint32_t* wcnt, hipStream_t s)
+hipError_t launch_huff_prep(const FieldDesc* F, int nf, uint32_t units, uint32_t* wcnt, uint32_t* soff,
+                            hipStream_t s)
 {
     if (!units) return hipSuccess;
-    hipLaunchKernelGGL(k_huff_prep, dim3(units), dim3(kBlock), 0, s, F, nf, wcnt);
+    hipLaunchKernelGGL(k_huff_prep, dim3(units), dim3(kBlock), 0, s, F, nf, wcnt, soff);
     return hipGetLastError();
 }
 
 hipError_t launch_huff_decode(const FieldDesc* F, int nf, uint32_t units, const uint32_t* woff,
-                              const uint8_t* tabs, size_t tab_stride, hipStream_t s)
+                              const uint32_t* soff, const uint8_t* tabs, size_t tab_stride,
+                              hipStream_t s)
 {
     if (!units) return hipSuccess;
-    hipLaunchKernelGGL(k_huff_decode, dim3(units), dim3(kDecBlock), 0, s, F, nf, woff, tabs, tab_stride);
+    hipLaunchKernelGGL(k_huff_decode, dim3(units), dim3(kDecLanes), 0, s, F, nf, woff, soff, tabs,
+                       tab_stride);
     return hipGetLastError();
 }
 

@@ -146,8 +146,9 @@ __global__ __launch_bounds__(kBlock) void k_rle_len(const FieldDesc* __restrict_
 }
 
 // ------------------------------------------------------------- decoding
-// run lengths from the archive into the batch-wide array; zero-length runs
-// are malformed
+// Run lengths from the archive into the batch-wide array.  A run must be
+// non-empty and no longer than the field; the scan that follows works modulo
+// 2^32, so the cover check below also needs the starts to increase.
 __global__ __launch_bounds__(kBlock) void k_rle_prep(const FieldDesc* __restrict__ F, int nf,
                                                      uint32_t* __restrict__ starts)
 {
@@ -157,19 +158,28 @@ __global__ __launch_bounds__(kBlock) void k_rle_prep(const FieldDesc* __restrict
     const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
     if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
     const uint32_t L = ((const EBC_G uint32_t*)(fd.arc + fd.off_rlen))[k];
-    if (L == 0) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
+    if (L == 0 || (uint64_t)L > fd.n) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
     starts[fd.rle_base + k] = L;
 }
 
-// runs must cover the field exactly
-__global__ void k_rle_check(const FieldDesc* __restrict__ F, int nf, const uint32_t* __restrict__ starts)
+// After the scan: the runs must cover the field exactly.  With every length
+// in [1, n], the relative starts (mod 2^32) increase strictly exactly when no
+// prefix sum wrapped, and then the last one is the true total, which must
+// equal n.  One thread per run (the run-length prep grid).
+__global__ __launch_bounds__(kBlock) void k_rle_check(const FieldDesc* __restrict__ F, int nf,
+                                                      const uint32_t* __restrict__ starts)
 {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+    const uint32_t t = blockIdx.x;
+    const int f = find_field<&FieldDesc::rl_base>(F, nf, t);
     const FieldDesc& fd = F[f];
-    if (fd.codec_hdr != ARC_RLE) return;
-    const uint32_t total = starts[fd.rle_base + fd.n_runs_hdr] - starts[fd.rle_base];
-    if ((uint64_t)total != fd.n) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
+    const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
+    if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
+    const uint32_t* S = starts + fd.rle_base;
+    const uint32_t s0 = S[0];
+    const uint32_t a = S[k] - s0, b = S[k + 1] - s0;
+    bool bad = b <= a;
+    if (k + 1 == fd.n_runs_hdr && (uint64_t)b != fd.n) bad = true;
+    if (bad) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
 }
 
 __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restrict__ F, int nf,
@@ -275,7 +285,7 @@ hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint
     hipLaunchKernelGGL(k_rle_prep, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
     hipError_t e = launch_scan(starts, n_starts, tmp, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_rle_check, dim3((nf + 63) / 64), dim3(64), 0, s, F, nf, starts);
+    hipLaunchKernelGGL(k_rle_check, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
     if (rt_units) hipLaunchKernelGGL(k_rle_expand, dim3(rt_units), dim3(kBlock), 0, s, F, nf, starts);
     return hipGetLastError();
 }

@@ -132,3 +132,16 @@ def test_tuning_changes_workspace_plan_not_validity(L):
     assert ebc.ebc_set_tuning([]) == 0
     assert ebc.ebc_compress_workspace_size(3, (100, 100, 100), p) == base
     assert all(s > 0 for s in sizes)
+
+
+def test_batch_unit_totals_beyond_32_bits_are_rejected(L):
+    """Two 2D fields of 1 x 3e9 hold 3e9 outlier row segments each: the batch
+    total passes 2^32, which the 32-bit unit indices of the kernels cannot
+    address, so sizing (host only) refuses the batch instead of wrapping."""
+    p = ebc.make_params(1e-4)
+    one = ebc.ebc_field(d_field=None, rank=2, reserved=0, dims=(C.c_uint64 * 3)(1, 3_000_000_000, 1),
+                        d_out=None, out_cap=0)
+    assert ebc.ebc_batch_compress_workspace_size([one], p) > 0
+    with pytest.raises(ebc.EbcError) as ei:
+        ebc.ebc_batch_compress_workspace_size([one, one], p)
+    assert ei.value.status == ebc.EBC_ERR_DIMS

@@ -245,19 +245,16 @@ def test_corrupt_archives_rejected(E):
         elif mutate == "truncate":
             b = b[:-16]
         elif mutate == "bits":
-            info = O.archive_info(raw.tobytes())
-            ob = (128 + info["n_bins"] + 15) & ~15
-            b[ob:ob + 4] = np.frombuffer(np.uint32(7).tobytes(), np.uint8)
+            # the first sub-chunk's bit count off by one
+            ob = O.sections(raw.tobytes())["layout"]["sbits"]
+            v = int(b[ob:ob + 2].view(np.uint16)[0]) + 1
+            b[ob:ob + 2] = np.frombuffer(np.uint16(v).tobytes(), np.uint8)
         else:
             s = O.sections(raw.tobytes())
             if s["info"]["n_outliers"] == 0:
                 continue
-            info = s["info"]
             # point the first outlier at a non-placeholder code
-            nch, nw = info["n_a"], info["n_words"]
-            ob = (128 + info["n_bins"] + 15) & ~15
-            ow = (ob + 4 * nch + 15) & ~15
-            oo = (ow + 4 * nw + 15) & ~15
+            oo = s["off_oidx"]
             it = O.intermediates(x, 1e-4)
             nz = int(np.flatnonzero(it["q"].ravel() != 0)[0])
             b[oo:oo + 4] = np.frombuffer(np.uint32(nz).tobytes(), np.uint8)
@@ -298,12 +295,8 @@ def test_3d_corrupt_outlier_rejected(E):
     x = rng_field((24, 40, 33), 25, "lognormal")
     raw = E.compress(dev(x), 1e-4).cpu().numpy().copy()
     s = O.sections(raw.tobytes())
-    info = s["info"]
-    assert info["n_outliers"] > 0
-    nch, nw = info["n_a"], info["n_words"]
-    ob = (128 + info["n_bins"] + 15) & ~15
-    ow = (ob + 4 * nch + 15) & ~15
-    oo = (ow + 4 * nw + 15) & ~15
+    assert s["info"]["n_outliers"] > 0
+    oo = s["off_oidx"]
     it = O.intermediates(x, 1e-4)
     nz = int(np.flatnonzero(it["q"].ravel() != 0)[0])
     b = raw.copy()
@@ -345,3 +338,37 @@ def test_full_size_3d_bench_workload(E):
     del xd
     y = E.decompress(a)
     np.testing.assert_array_equal(bits(y.cpu().numpy()), bits(want))
+
+
+def test_corrupt_rle_archives_rejected(E):
+    """Run lengths that are zero, longer than the field, or that wrap modulo
+    2^32 while every one stays within the field and their sum modulo 2^32 is
+    still N, are rejected on both sides: the runs must cover the field
+    exactly, one non-empty run after the other."""
+    n = 1 << 20
+    x = np.random.default_rng(7).standard_normal(n).astype(np.float32)
+    raw = np.frombuffer(O.compress(x, 1e-2, codec="rle"), np.uint8).copy()
+    info = O.archive_info(raw.tobytes())
+    R = info["n_a"]
+    assert info["codec"] == O.ARC_RLE and R > 8192
+    off_len = (128 + 2 * R + 15) & ~15
+    lens = raw[off_len:off_len + 4 * R].view(np.uint32).copy()
+    for mutate in ("zero", "long", "wrap"):
+        L = lens.astype(np.uint64)
+        if mutate == "zero":
+            # a zero-length run, its length moved to the next run (sum unchanged)
+            L[1] += L[0]
+            L[0] = 0
+        elif mutate == "long":
+            L[0] = n + 1
+        else:
+            # 4096 runs of length n add 2^32 (zero modulo 2^32); the last run
+            # takes what they displaced, so the sum modulo 2^32 is n again
+            moved = int(L[:4096].sum())
+            L[:4096] = n
+            L[-1] += moved
+            assert int(L.max()) <= n and int(L.sum()) % (1 << 32) == n
+        b = raw.copy()
+        b[off_len:off_len + 4 * R] = L.astype(np.uint32).view(np.uint8)
+        assert O.decompress_status(b.tobytes()) == -9, mutate
+        assert E.decompress_status(dev(b)) == E.EBC_ERR_ARCHIVE, mutate

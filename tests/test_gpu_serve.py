@@ -126,3 +126,52 @@ def test_oversized_request_is_rejected(E, bases):
     r = S.submit(Request("compress", 0.0, x=bases[(3, "grf")], eb=1e-3))
     assert r.status == E.EBC_ERR_OUT_TOO_SMALL
     assert not S.busy()
+
+
+def test_retained_workspaces_stay_within_budget(E, bases):
+    """A burst of large requests grows the slot workspaces; the small requests
+    after it must not push the device memory the server holds past its budget
+    (idle slots' workspaces count, and are given back when needed)."""
+    from paper_2105_12912_amd.serve import Request, Server
+
+    torch.cuda.synchronize()
+    base_mem = torch.cuda.memory_allocated()
+    budget = 96 << 20
+    S = Server(hbm_budget=budget, slots=3, max_batch=4)
+    big = [bases[(3, "lognormal")], bases[(2, "grf")], bases[(1, "grf")]]
+    reqs = [S.submit(Request("compress", 0.0, x=x, eb=1e-3)) for x in big]
+    small = small_stream(63, 24, 1e9)
+    reqs += [S.submit(Request("compress", 0.0, x=prefix(bases, sp)[:64], eb=sp["eb"]))
+             for sp in small]
+    peak = 0
+    while S.busy():
+        for r in S.poll():
+            assert r.status == 0
+            r.out = None  # results are the caller's; none are kept here
+        peak = max(peak, torch.cuda.memory_allocated() - base_mem)
+    assert S.peak_in_use <= budget
+    # slack: the per-batch result records and allocator rounding
+    assert peak <= budget + (4 << 20), (peak, budget)
+
+
+def test_input_written_asynchronously_before_submit(E, bases):
+    """The slot stream waits for the submitting stream: an input produced by
+    work still queued on the caller's stream is compressed after it is ready."""
+    from paper_2105_12912_amd.serve import Request, Server
+
+    src = bases[(3, "lognormal")]
+    want = E.compress(src, 1e-4, "rel")
+    S = Server(hbm_budget=1 << 30, slots=2, max_batch=4)
+    side = torch.cuda.Stream()
+    reqs = []
+    with torch.cuda.stream(side):
+        for _ in range(4):
+            x = torch.empty_like(src)
+            torch.cuda._sleep(2_000_000)  # keeps the copy below queued for a while
+            x.copy_(src)
+            reqs.append(S.submit(Request("compress", 0.0, x=x, eb=1e-4)))
+    S.drain()
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert r.status == 0
+        assert r.out.numel() == want.numel() and torch.equal(r.out, want)

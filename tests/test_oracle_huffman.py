@@ -184,43 +184,52 @@ def test_decision_single_symbol_is_rle():
 def test_huffman_encode_decode_roundtrip(h):
     rng = np.random.default_rng(31)
     p = h.astype(np.float64) / h.sum()
-    for hc in (64, 1024):
-        n = int(rng.integers(1, 5000))
+    for hc in (64, 1024, 4096):
+        n = int(rng.integers(1, 9000))
         q = rng.choice(h.size, size=n, p=p).astype(np.uint16)
         ln = O.huffman_lengths(O.histogram(q, h.size))
         code = O.canonical_codes(ln)
-        ent, words = O.huffman_encode(q, ln, code, hc)
-        # chunk entries: the code-length sum in the low half and the bit offset
-        # of the chunk's symbol hc/2 (the sum itself for a short chunk) in the
-        # high half; words per chunk are ceil(bits/32)
-        bits = ent & 0xFFFF
-        for c in range(ent.size):
-            chunk = ln[q[c * hc:(c + 1) * hc]].astype(np.int64)
-            assert bits[c] == int(chunk.sum())
-            mid = int(chunk[:hc // 2].sum()) if chunk.size > hc // 2 else int(chunk.sum())
-            assert ent[c] >> 16 == mid
-        assert words.size == int(((bits.astype(np.int64) + 31) // 32).sum())
+        sb, words = O.huffman_encode(q, ln, code, hc)
+        # one u16 entry per sub-chunk of min(hc, 256) symbols: the sum of its
+        # code lengths; a chunk takes ceil(sum of its sub-chunks / 32) words
+        hs = min(hc, 256)
+        assert O.sub_chunk(hc) == hs and sb.size == (n + hs - 1) // hs
+        for k in range(sb.size):
+            assert int(sb[k]) == int(ln[q[k * hs:(k + 1) * hs]].astype(np.int64).sum())
+        per = hc // hs
+        chunk_bits = [int(sb[c * per:(c + 1) * per].astype(np.int64).sum())
+                      for c in range((n + hc - 1) // hc)]
+        for c, b in enumerate(chunk_bits):
+            assert b == int(ln[q[c * hc:(c + 1) * hc]].astype(np.int64).sum())
+        assert words.size == sum((b + 31) // 32 for b in chunk_bits)
         # payload never below one bit per symbol (CR <= 32 for fp32, Sec. II-B.1)
-        assert int(bits.astype(np.int64).sum()) >= n
-        np.testing.assert_array_equal(O.huffman_decode(ent, words, n, ln, hc), q)
-        # a wrong midpoint is a corrupt archive
-        if ent.size:
-            bad = ent.copy()
-            bad[0] ^= 1 << 16
-            with pytest.raises(O.OracleError):
-                O.huffman_decode(bad, words, n, ln, hc)
+        assert sum(chunk_bits) >= n
+        np.testing.assert_array_equal(O.huffman_decode(sb, words, n, ln, hc), q)
+        # a sub-chunk count that is off by one is a corrupt archive
+        if sb.size > 1:
+            for k in (0, sb.size - 1):
+                bad = sb.copy()
+                bad[k] += 1
+                with pytest.raises(O.OracleError):
+                    O.huffman_decode(bad, words, n, ln, hc)
 
 
-def test_huffman_chunk_entry_without_midpoint_above_1024():
-    """For chunks longer than 1024 symbols the entry is the plain bit count."""
+def test_huffman_sub_chunks_in_long_chunks():
+    """Chunks longer than 256 symbols are cut into 256-symbol sub-chunks whose
+    bits follow each other inside the chunk (no padding between them)."""
     rng = np.random.default_rng(32)
     q = rng.integers(0, 5, size=5000).astype(np.uint16)
     ln = O.huffman_lengths(O.histogram(q, 5))
     code = O.canonical_codes(ln)
-    ent, words = O.huffman_encode(q, ln, code, 2048)
-    for c in range(ent.size):
-        assert ent[c] == int(ln[q[c * 2048:(c + 1) * 2048]].astype(np.int64).sum())
-    np.testing.assert_array_equal(O.huffman_decode(ent, words, q.size, ln, 2048), q)
+    sb, words = O.huffman_encode(q, ln, code, 2048)
+    assert sb.size == (5000 + 255) // 256
+    for k in range(sb.size):
+        assert sb[k] == int(ln[q[k * 256:(k + 1) * 256]].astype(np.int64).sum())
+    # the stream of chunk 0 is the concatenation of its 8 sub-chunks
+    bits = "".join(format(int(code[s]), f"0{int(ln[s])}b") for s in q[:2048])
+    got = "".join(format(int(w), "032b") for w in words)[:len(bits)]
+    assert got == bits
+    np.testing.assert_array_equal(O.huffman_decode(sb, words, q.size, ln, 2048), q)
 
 
 def test_huffman_bitstream_layout_msb_first():
@@ -231,7 +240,7 @@ def test_huffman_bitstream_layout_msb_first():
     assert list(ln) == [1, 2, 2] and list(code) == [0, 2, 3]
     q = np.array([0, 1, 2, 0], np.uint16)
     bits, words = O.huffman_encode(q, ln, code, 64)
-    assert list(bits) == [6 | (6 << 16)]  # 6 bits; no symbol 32, so the midpoint is the end
+    assert list(bits) == [6]  # one sub-chunk of 6 bits
     assert list(words) == [0b010110 << 26]
 
 

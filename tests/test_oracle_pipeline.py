@@ -218,11 +218,13 @@ def test_header_fields():
     a = O.compress(x, 1e-4)
     b = np.frombuffer(a, np.uint8)
     assert bytes(b[:4]) == b"EBC1"
-    assert int(b[4:6].view(np.uint16)[0]) == 1
+    assert int(b[4:6].view(np.uint16)[0]) == 2  # format version
     assert int(b[8]) == 2  # rank
+    assert int(b[11]) == 0  # fp32
     assert int(b[12:16].view(np.uint32)[0]) == 1024
     assert list(b[16:40].view(np.uint64)) == [56, 40, 1]
     assert list(b[40:52].view(np.uint32)) == [16, 16, 1]
     assert int(b[52:56].view(np.uint32)[0]) == 1024
     assert int(b[112:120].view(np.uint64)[0]) == len(a)
+    assert int(b[120:124].view(np.uint32)[0]) == 256  # Huffman sub-chunk symbols
     assert len(a) % 16 == 0

@@ -43,17 +43,30 @@ WORKLOADS = {
 
 # kernel stage -> algorithmic bytes per launch (n elements, o outliers, w words, r runs);
 # the 3D reconstruction reads no outlier deltas (its fix-up kernel does)
-def algo_bytes(stage: str, n: int, o: int, w: int, r: int, n_bins: int, rank: int = 3) -> float | None:
+def algo_bytes(stage: str, n: int, o: int, w: int, r: int, n_bins: int, rank: int = 3,
+               codec: int = 0, elem: int = 4) -> float | None:
+    """Bytes a stage must move (the method's, not the kernels' actual traffic).
+    codec 0 Huffman, 1 RLE, 3 RLE+VLE; elem: bytes per input value."""
+    if codec == 0:
+        enc_count, enc_write = 2 * n, 2 * n + 4 * w
+        dec = 4 * w + 2 * n
+    elif codec == 1:
+        # run flags from the codes; (value, start) per run, then lengths
+        enc_count, enc_write = 2 * n, 2 * n + 6 * r + 8 * r
+        dec = None
+    else:
+        enc_count, enc_write = 2 * n, 2 * r + 4 * w + 8 * r
+        dec = 4 * w + 2 * r
     table = {
-        "range": 4 * n,
-        "construct": 4 * n + 2 * n + 8 * o,
-        "encode_count": 2 * n,
-        "encode_write": 2 * n + 4 * w,
+        "range": elem * n,
+        "construct": elem * n + 2 * n + 8 * o,
+        "encode_count": enc_count,
+        "encode_write": enc_write,
         "outlier_write": 8 * o,
-        "huffman_decode": 4 * w + 2 * n,
+        "huffman_decode": dec,
         "rle_decode": 6 * r + 2 * n,
         "outlier_scatter": 12 * o,
-        "reconstruct": 2 * n + 4 * n + (4 * o if rank < 3 else 0),
+        "reconstruct": 2 * n + elem * n + (4 * o if rank < 3 else 0),
     }
     return table.get(stage)
 
@@ -105,6 +118,157 @@ def cpu_baseline(x: np.ndarray, eb: float, ref_bytes: bytes | None):
     ), a, y
 
 
+def _timed_pairs(fn_c, fn_d, reps: int, flush=None):
+    """Median compress and decompress times (ms) with HIP events on the
+    current stream; flush() (outside the events) runs before every call."""
+    import torch
+
+    s = torch.cuda.current_stream()
+    tc, td = [], []
+    for _ in range(reps):
+        if flush:
+            flush()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn_c()
+        e1.record(s)
+        if flush:
+            flush()
+        e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2.record(s)
+        fn_d()
+        e3.record(s)
+        torch.cuda.synchronize()
+        tc.append(e0.elapsed_time(e1))
+        td.append(e2.elapsed_time(e3))
+    tc.sort()
+    td.sort()
+    return tc[len(tc) // 2], td[len(td) // 2]
+
+
+def bench_field(xd, eb: float, codec: str = "auto", reps: int = 5, ref=None) -> dict:
+    """One field through the plain path: compress / decompress rates, the
+    per-stage breakdown of one instrumented pass with each stage's
+    algorithmic bytes, and (ref = oracle archive) byte equality."""
+    import torch
+
+    from paper_2105_12912_amd import ebc
+
+    ws = ebc.Workspace(xd.device)
+    elem = xd.element_size()
+    rank, dims = ebc.field_rank_dims(xd)
+    p = ebc.make_params(eb, "rel", 1024, codec, 1024, ebc._dtype_code(xd))
+    out = torch.empty(ebc.ebc_compress_bound(rank, dims, p), dtype=torch.uint8, device=xd.device)
+    y = torch.empty_like(xd)
+    state = {}
+
+    def comp():
+        state["a"] = ebc.compress(xd, eb, "rel", codec=codec, workspace=ws, out=out)
+
+    def dec():
+        ebc.decompress(state["a"], out=y, workspace=ws)
+
+    comp()
+    dec()
+    tc, td = _timed_pairs(comp, dec, reps)
+    a, cs = ebc.compress(xd, eb, "rel", codec=codec, stats=True, workspace=ws, out=out)
+    _, ds = ebc.decompress(a, out=y, stats=True, workspace=ws)
+    n, o, w, r = xd.numel(), cs.n_outliers, cs.n_words, cs.n_runs
+    stages = {"c:" + k: v for k, v in cs.stages().items()}
+    stages.update({"d:" + k: v for k, v in ds.stages().items()})
+    roof = {}
+    for key, t in stages.items():
+        b = algo_bytes(key.split(":", 1)[1], n, o, w, r, 1024, xd.dim(), cs.codec, elem)
+        if b is None or t <= 0:
+            continue
+        ach = b / (t / 1e3) / 1e9
+        roof[key] = dict(ms=round(t, 5), algo_bytes=int(b), GBps=round(ach, 1),
+                         frac=round(ach / HBM_PEAK_GBPS, 4))
+    gb = xd.numel() * elem / 1e9
+    res = {
+        "elements": n, "input_bytes": n * elem, "eb_rel": eb, "codec_request": codec,
+        "codec": ["huffman", "rle", "const", "rle_vle"][cs.codec],
+        "compress_ms": round(tc, 4), "decompress_ms": round(td, 4),
+        "compress_GBps": round(gb / (tc / 1e3), 2), "decompress_GBps": round(gb / (td / 1e3), 2),
+        "roundtrip_GBps": round(gb / ((tc + td) / 1e3), 2),
+        "archive_bytes": a.numel(), "compression_ratio": round(n * elem / a.numel(), 3),
+        "n_runs": r, "n_words": w, "n_outliers": o,
+        "max_abs_err_ok": bool((y.double() - xd.double()).abs().max().item()
+                               <= eb * (xd.max().item() - xd.min().item())),
+        "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+        "kernel_roofline": roof,
+    }
+    if ref is not None:
+        res["archive_equals_oracle"] = a.cpu().numpy().tobytes() == ref
+    del ws, out, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_cold(xd, eb: float, reps: int = 5) -> dict:
+    """Construction and reconstruction with the 256 MB last-level cache
+    flushed before each call (a 1 GiB buffer written in between): the cold
+    numbers, next to the warm ones of the main timing."""
+    import torch
+
+    from paper_2105_12912_amd import ebc
+
+    ws = ebc.Workspace(xd.device)
+    flush_buf = torch.empty(1 << 28, dtype=torch.float32, device=xd.device)
+
+    def flush():
+        flush_buf.fill_(1.0)
+
+    a = ebc.compress(xd, eb, "rel", workspace=ws)
+    y = ebc.decompress(a, workspace=ws)
+    tc, td = [], []
+    for _ in range(reps):
+        flush()
+        _, cs = ebc.compress(xd, eb, "rel", stats="construct", workspace=ws)
+        flush()
+        _, ds = ebc.decompress(a, out=y, stats="reconstruct", workspace=ws)
+        tc.append(cs.stages()["construct"])
+        td.append(ds.stages()["reconstruct"])
+    tc.sort()
+    td.sort()
+    n = xd.numel()
+    out = {}
+    for name, t, b in (("construct", tc[len(tc) // 2], 6 * n), ("reconstruct", td[len(td) // 2], 6 * n)):
+        ach = b / (t / 1e3) / 1e9
+        out[name] = dict(ms=round(t, 5), algo_bytes=b, GBps=round(ach, 1), frac=round(ach / HBM_PEAK_GBPS, 4))
+    out["flush"] = "1 GiB device buffer written before every timed call (evicts the 256 MB last-level cache)"
+    del flush_buf, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_all_cores(x: np.ndarray, eb: float, procs: int | None = None) -> dict:
+    """The oracle on every host core: the field cut into z-slabs of whole
+    8-plane chunks, each compressed and decompressed by its own process (the
+    chunks are independent, so the work is the same; the archives are per
+    slab)."""
+    import multiprocessing as mp
+
+    procs = procs or min(os.cpu_count() or 1, 64)
+    nz = x.shape[0]
+    cuts = sorted(set([0] + [((nz * k // procs) // 8) * 8 for k in range(1, procs)] + [nz]))
+    slabs = [np.ascontiguousarray(x[a:b]) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(len(slabs)) as pool:
+        pool.starmap(_oracle_roundtrip, [(s_, eb) for s_ in slabs])
+    t = time.perf_counter() - t0
+    return dict(value=round(x.nbytes / 1e9 / t, 4), unit="GB/s", cores=len(slabs), kind="oracle",
+                sample=f"whole field in {len(slabs)} z-slabs of whole 8^3 chunks, one process each, "
+                       f"compress + decompress: {t:.2f}s")
+
+
+def _oracle_roundtrip(x, eb):
+    from oracle import oracle as O
+
+    O.decompress(O.compress(x, eb, "rel"))
+
+
 def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
     """The 64-field mixed-rank batch: one graph replay of the batched path
     against the same fields through sequential plain calls (each of which
@@ -119,10 +283,34 @@ def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
     torch.cuda.synchronize()
     nbytes = sum(4 * x.numel() for x in fields)
     table, report = [], {}
+    s = torch.cuda.current_stream()
+    default_ms = None
     if autotune_on:
+        # the batched path with the default table first, for the tuner's gain
+        print("[bench] batch: default tiles", file=sys.stderr, flush=True)
+        ebc.ebc_set_tuning([])
+        B0 = batch.BatchCompress(fields, eb)
+        B0.capture()
+        arcs0 = B0.archives()
+        D0 = batch.BatchDecompress(arcs0)
+        D0.capture()
+        default_ms = []
+        for fn in (B0.replay, D0.replay):
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(s)
+                fn()
+                e1.record(s)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            ts.sort()
+            default_ms.append(ts[len(ts) // 2])
+        del B0, D0, arcs0
+        torch.cuda.empty_cache()
         print("[bench] autotuning tile shapes", file=sys.stderr, flush=True)
         table, report = autotune.tune(fields, eb)
-    s = torch.cuda.current_stream()
 
     def timed(fn, n):
         ts = []
@@ -189,8 +377,14 @@ def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
         "batched_equals_plain": {"archives": bool(same_c), "reconstructions": bool(same_d)},
         "compression_ratio": round(nbytes / sum(a.numel() for a in arcs), 3),
         "autotune": {"classes": len(table),
-                     "table": [[e["rank"], e["nx_class"], e["n_class"], e["tile_wx"], e["grid"]]
-                               for e in table]},
+                     "table": [[e["rank"], e["nx_class"], e["n_class"], e["tile_wx"], e["grid"], e.get("scan_direct", 0)]
+                               for e in table],
+                     "default_table_batched_ms": (None if default_ms is None else
+                                                  {"compress": round(default_ms[0], 3),
+                                                   "decompress": round(default_ms[1], 3)}),
+                     "gain_over_default": (None if default_ms is None else
+                                           {"compress": round(default_ms[0] / t_batch_c, 3),
+                                            "decompress": round(default_ms[1] / t_batch_d, 3)})},
         "path": "batched = one HIP-graph replay of ebc_batch_*_async; plain = sequential "
                 "ebc_compress / ebc_decompress, one synchronisation each",
     }
@@ -200,8 +394,10 @@ def bench_batched(eb: float, autotune_on: bool, reps: int = 5):
     return res
 
 
-def bench_serving(seconds: float, warmup: float, rate: float = 200.0):
-    """The Poisson request stream through the continuous-batching loop."""
+def bench_serving(seconds: float, warmup: float, rate: float = 200.0, pressure: bool = True):
+    """The Poisson request stream through the continuous-batching loop, then
+    (pressure) the same request mix at ten times the rate for a few seconds
+    under a smaller HBM budget, where requests queue for slots and memory."""
     import torch
 
     from paper_2105_12912_amd import serve, synth
@@ -230,7 +426,20 @@ def bench_serving(seconds: float, warmup: float, rate: float = 200.0):
                             "not measured), sizes log-uniform 1 MB-2 GB fp32, rank 1/2/3, GRF or "
                             "sparse lognormal, rel eb from {1e-2, 1e-3, 1e-4}, half decompress "
                             "of earlier archives; inputs are prefix views of device-resident fields")
-    del bases, server
+    del server
+    if pressure:
+        prate, psec = 10 * rate, 5.0
+        pstream = synth.request_stream(seed=6, rate=prate, duration=psec)
+        pserver = serve.Server(hbm_budget=24 << 30, slots=4, max_batch=32)
+        print(f"[bench] serving under pressure: {len(pstream)} requests over {psec:.0f} s",
+              file=sys.stderr, flush=True)
+        ps = serve.run_stream(pserver, pstream, make_input, warmup=0.5)
+        ps.update(workload=f"the same mix at {prate:.0f} req/s for {psec:.0f} s under a 24 GiB budget "
+                           "(offered load above what the device sustains: requests wait for slots "
+                           "and memory, batches form)")
+        summary["pressure"] = ps
+        del pserver
+    del bases
     torch.cuda.empty_cache()
     return summary
 
@@ -244,9 +453,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-field batched comparison")
-    ap.add_argument("--serve-seconds", type=float, default=12.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the serving stream (0 skips it)")
     ap.add_argument("--no-autotune", action="store_true", help="batched comparison with default tiles")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the second bound, run-length, fp64, estimator and cold-cache sections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (counter calibration)")
     args = ap.parse_args()
@@ -410,12 +621,50 @@ def main():
             "reconstruction_bits_equal": bool(np.array_equal(oy.view(np.uint32),
                                                              y.cpu().numpy().view(np.uint32))),
         }
+    if not args.no_extras and args.workload == "nyx512":
+        print("[bench] cold-cache construct / reconstruct", file=sys.stderr, flush=True)
+        result["cold_cache"] = bench_cold(xd, eb)
+        print("[bench] second bound (rel 1e-3)", file=sys.stderr, flush=True)
+        result["nyx512_rel_1e-3"] = bench_field(xd, 1e-3)
+        result["nyx512_rel_1e-3"]["workload"] = "the same 512^3 field at rel eb 1e-3"
+        print("[bench] estimator", file=sys.stderr, flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        est = ebc.estimate(xd, eb, samples=1 << 20, seed=1)
+        e1.record(s)
+        torch.cuda.synchronize()
+        _, cst = ebc.compress(xd, eb, "rel", stats=True, workspace=ws)
+        result["estimate"] = {
+            "ms": round(e0.elapsed_time(e1), 4), "samples": 1 << 20,
+            "entropy": est["entropy"], "p1": est["p1"], "bits_lo": est["bits_lo"],
+            "bits_hi": est["bits_hi"], "actual_avg_bits": cst.huff_bits / n,
+            "codec_hint": est["codec_hint"], "roughness": est["roughness"],
+            "note": "ms covers value range, construction, histogram and the estimates (no codebook)",
+        }
+        print("[bench] fp64 field", file=sys.stderr, flush=True)
+        x64 = xd.double()
+        result["fp64"] = bench_field(x64, eb)
+        result["fp64"]["workload"] = "the 512^3 field as fp64, rel eb 1e-4"
+        del x64
+        torch.cuda.empty_cache()
+        print("[bench] run-length workloads", file=sys.stderr, flush=True)
+        xs = torch.from_numpy(synth.sparse_background_1d(120_000_000)).to(dev)
+        result["rle"] = bench_field(xs, 1e-2, "auto")
+        result["rle"]["workload"] = ("1D 1.2e8 fp32, constant except 0.4% random-walk blocks "
+                                     "(background-dominated), rel eb 1e-2, 1.09-bit rule")
+        result["rle_vle"] = bench_field(xs, 1e-2, "auto_vle")
+        result["rle_vle"]["workload"] = "the same field, the rule's run-length branch with VLE on"
+        del xs
+        torch.cuda.empty_cache()
+        if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+            print("[bench] cpu baseline, all cores", file=sys.stderr, flush=True)
+            result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(x, eb, min(16, os.cpu_count() or 1))
     if not args.no_batch:
         del xd, ydev, out_buf, ws
         torch.cuda.empty_cache()
         result["batched"] = bench_batched(eb, not args.no_autotune)
     if args.serve_seconds > 0:
-        result["serving"] = bench_serving(args.serve_seconds, min(2.0, args.serve_seconds / 4))
+        result["serving"] = bench_serving(args.serve_seconds, min(5.0, args.serve_seconds / 4))
     print(json.dumps(result))
 
 

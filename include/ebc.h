@@ -23,9 +23,10 @@
  *     All device work is enqueued on it in order.  Calls that return a host
  *     value computed on the device (out_size, stats) synchronise that stream
  *     once; the *_async variants never synchronise.
- *   - A field is fp32, row-major with x fastest; dims = {nx, ny, nz}; unused
- *     trailing dims must be 1; rank is 1, 2 or 3; the element count must be
- *     < 2^32.
+ *   - A field is fp32 (or fp64 with dtype EBC_F64), row-major with x fastest;
+ *     dims = {nx, ny, nz}; unused trailing dims must be 1; rank is 1, 2 or 3;
+ *     the element count must be < 2^32.  An archive records the element type;
+ *     decompression writes elements of that type.
  *   - Calls on distinct workspaces are independent and may run concurrently
  *     on different streams.  The library keeps no mutable global state.
  */
@@ -59,16 +60,26 @@ extern "C" {
 #define EBC_EB_ABS 0
 #define EBC_EB_REL 1
 
-/* codec request: AUTO applies the 1.09-bit rule (Sec. I, Sec. III-B.2) */
+/* codec request: AUTO applies the 1.09-bit rule (Sec. I, Sec. III-B.2) and
+   picks the Huffman or the run-length workflow; AUTO_VLE applies the same
+   rule, and its run-length branch Huffman-codes the run values as well
+   (the workflow "RLE with optional VLE" of Sec. III-A, VLE switched on);
+   RLE_VLE forces that branch. */
 #define EBC_CODEC_AUTO 0
 #define EBC_CODEC_HUFFMAN 1
 #define EBC_CODEC_RLE 2
+#define EBC_CODEC_RLE_VLE 3
+#define EBC_CODEC_AUTO_VLE 4
 
 /* codec recorded in an archive */
 #define EBC_ARC_HUFFMAN 0
 #define EBC_ARC_RLE 1
 #define EBC_ARC_CONST 2
 #define EBC_ARC_RLE_VLE 3  /* RLE with the run values Huffman-coded (Sec. III-A) */
+
+/* element type of a field (input of compression, output of decompression) */
+#define EBC_F32 0
+#define EBC_F64 1 /* fp64 fields through the same integer core (Sec. III: Huffman CR <= 64) */
 
 typedef struct ebc_params {
     int32_t eb_mode;     /* EBC_EB_ABS or EBC_EB_REL */
@@ -78,6 +89,8 @@ typedef struct ebc_params {
                             4..65536; this GPU path implements n_bins <= 4096 */
     uint32_t huff_chunk; /* symbols per Huffman chunk: 0 selects 1024; power of two;
                             this GPU path implements 64..4096 */
+    int32_t dtype;       /* EBC_F32 or EBC_F64: element type of the field to compress */
+    int32_t reserved;    /* 0 */
 } ebc_params;
 
 /* stats flags (in ebc_stats.flags) */
@@ -103,7 +116,31 @@ typedef struct ebc_stats {
     const char* time_only; /* in: with TIMING, NULL times every stage; else only the stage
                               of this name gets an event pair (one stage reported), so
                               that the rest of the call runs uninstrumented */
+    /* out (compression): the histogram estimates of Sec. III-B.1, see ebc_estimate */
+    double entropy;      /* H of the quant-code histogram, bits per symbol */
+    double p1;           /* probability of the most likely code */
+    double r_lo, r_hi;   /* Huffman redundancy bounds: H + r_lo <= avg bits <= H + r_hi */
+    int32_t predict;     /* workflow the bounds predict: 1 run-length, 0 Huffman, 2 undecided */
+    int32_t pad;
 } ebc_stats;
+
+/* Compressibility estimates (Sec. III-B) of a field's quant-codes. */
+#define EBC_MADO_DMAX 200 /* largest madogram distance (Sec. III-B.2) */
+typedef struct ebc_estimates {
+    int32_t codec_hint;  /* 1 run-length, 0 Huffman, 2 undecided (the bounds straddle 1.09) */
+    int32_t pad;
+    double entropy;      /* H = -sum p_i log2 p_i over the code histogram (Sec. III-B.1) */
+    double p1;           /* probability of the most likely code */
+    double r_lo, r_hi;   /* redundancy bounds: R- = 1 - H(p1, 1-p1) for p1 > 0.4 (else 0;
+                            1 for a single code), R+ = p1 + 0.086 */
+    double bits_lo, bits_hi; /* H + r_lo and H + r_hi: bounds of the Huffman average bits */
+    uint64_t hist_max;   /* count of the most likely code */
+    uint64_t n_elems;
+    uint64_t samples;    /* madogram samples drawn (pairs past the end are skipped) */
+    double roughness;    /* sum of mado_sum / sum of mado_cnt over all distances */
+    uint64_t mado_sum[EBC_MADO_DMAX + 1]; /* pairs at distance d whose codes differ */
+    uint64_t mado_cnt[EBC_MADO_DMAX + 1]; /* pairs at distance d (index 0 unused) */
+} ebc_estimates;
 
 /* Library version (EBC_VERSION) and a static string for a status code. */
 int ebc_version(void);
@@ -129,7 +166,7 @@ int ebc_compress_workspace_size(int rank, const uint64_t dims[3], const ebc_para
    stats (host, nullable): filled after the synchronisation.
    Errors detected on the device (NaN/Inf, bound too small, output too small)
    are returned after that synchronisation; the output is then undefined. */
-int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+int ebc_compress(const void* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
                  void* d_out, uint64_t out_cap, uint64_t* out_size, void* d_ws,
                  uint64_t ws_bytes, void* stream, ebc_stats* stats);
 
@@ -138,12 +175,13 @@ int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const e
    d_result[0] and ((int32_t*)(d_result + 1))[0] once the stream reaches them.
    d_result must hold 16 bytes.  Host-detectable argument errors are returned
    immediately. */
-int ebc_compress_async(const float* d_field, int rank, const uint64_t dims[3],
+int ebc_compress_async(const void* d_field, int rank, const uint64_t dims[3],
                        const ebc_params* p, void* d_out, uint64_t out_cap, uint64_t* d_result,
                        void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* Parse a host copy of an archive header (at least 128 bytes).  Any output
-   pointer may be NULL.  p receives eb mode, eb, n_bins and the Huffman chunk. */
+   pointer may be NULL.  p receives eb mode, eb, n_bins, the Huffman chunk and
+   the element type. */
 int ebc_archive_info(const void* h_header, uint64_t header_bytes, int* rank, uint64_t dims[3],
                      ebc_params* p, int* codec, uint64_t* total_bytes);
 
@@ -153,13 +191,13 @@ int ebc_decompress_workspace_size(const void* h_header, uint64_t header_bytes, u
 /* Decompress a device-resident archive (size bytes) into d_out (out_elems
    fp32, device).  Reads the 128-byte header back to the host once, launches
    the decode, and synchronises once more to return the device-side status. */
-int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t out_elems,
+int ebc_decompress(const void* d_archive, uint64_t size, void* d_out, uint64_t out_elems,
                    void* d_ws, uint64_t ws_bytes, void* stream, ebc_stats* stats);
 
 /* As ebc_decompress with the header supplied by the caller (host copy) and no
    synchronisation; the int32 status lands in d_status (device). */
 int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t size,
-                         float* d_out, uint64_t out_elems, void* d_ws, uint64_t ws_bytes,
+                         void* d_out, uint64_t out_elems, void* d_ws, uint64_t ws_bytes,
                          int32_t* d_status, void* stream);
 
 /* ---------------------------------------------------------------------- */
@@ -167,7 +205,7 @@ int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t s
 /* launches (each kernel covers every field's tiles in one grid).           */
 /* ---------------------------------------------------------------------- */
 typedef struct ebc_field {
-    const float* d_field; /* input field (device) */
+    const void* d_field;  /* input field (device), of the batch's dtype */
     int32_t rank;
     uint32_t reserved;
     uint64_t dims[3];
@@ -201,7 +239,7 @@ typedef struct ebc_archive_ref {
     const void* d_archive; /* device */
     uint64_t size;
     const void* h_header;  /* host copy of the first 128 bytes */
-    float* d_out;          /* device output */
+    void* d_out;           /* device output, elements of the archive's type */
     uint64_t out_elems;
 } ebc_archive_ref;
 
@@ -216,8 +254,8 @@ int ebc_batch_decompress_async(int n, const ebc_archive_ref* refs, int32_t* d_st
                                void* d_ws, uint64_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------- */
-/* Tuning: tile shape and grid per (rank, shape class).  Tuning never       */
-/* changes the output bytes, only the launch geometry.                      */
+/* Tuning: tile shape, grid and scan schedule per (rank, shape class).      */
+/* Tuning never changes the output bytes, only the launch geometry.         */
 /* ---------------------------------------------------------------------- */
 typedef struct ebc_tuning_entry {
     int32_t rank;      /* 1, 2 or 3 */
@@ -227,7 +265,12 @@ typedef struct ebc_tuning_entry {
                           tile is tile_wx * 64 x (4/tile_wx) * 16 in 2D and
                           tile_wx * 32 x (4/tile_wx) * 8 x 8 in 3D; 0 = default */
     uint32_t grid;     /* persistent construction grid in workgroups, 64..16384;
-                          0 = default (2048) */
+                          0 = default (the workgroups the device holds at once) */
+    uint32_t scan_direct; /* scan schedule: a prefix sum of up to this many tiles of
+                          4096 items adds each tile's predecessors directly, a longer
+                          one scans the tile sums in a workgroup first; 0 = default
+                          (1024), at most 2^20.  A call takes the largest value among
+                          its fields' entries. */
 } ebc_tuning_entry;
 
 /* Replace the library's tuning table (n = 0 clears it).  This table is the
@@ -248,7 +291,7 @@ int ebc_shape_class(int rank, const uint64_t dims[3], uint32_t* nx_class, uint32
    d_q: N uint16 quant-codes; d_hist: n_bins uint32; d_oidx/d_oval: outlier
    indices (ascending) and int32 deltas, capacity N each; n_outliers (host)
    receives the count; ebx2 (host, nullable) the step.  Synchronises once. */
-int ebc_debug_construct(const float* d_field, int rank, const uint64_t dims[3],
+int ebc_debug_construct(const void* d_field, int rank, const uint64_t dims[3],
                         const ebc_params* p, uint16_t* d_q, uint32_t* d_hist, uint32_t* d_oidx,
                         int32_t* d_oval, uint64_t* n_outliers, double* ebx2, void* d_ws,
                         uint64_t ws_bytes, void* stream);

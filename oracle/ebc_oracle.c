@@ -603,6 +603,70 @@ void ora_dequant64(const int32_t* d, uint64_t n, double ebx2, double* out)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Compressibility estimates (Sec. III-B).                                   */
+/*                                                                          */
+/* From the histogram (Sec. III-B.1): entropy H = -sum p_i log2 p_i, the    */
+/* probability p1 of the most likely symbol, and bounds on the Huffman      */
+/* redundancy R = <b> - H: R+ = p1 + 0.086 always, R- = 1 - H(p1, 1 - p1)   */
+/* when p1 > 0.4 (else 0), so H + R- <= <b> <= H + R+ without a codebook.   */
+/* The workflow they predict: run-length coding when even the upper bound   */
+/* of <b> is at most 1.09 bits, Huffman when the lower bound exceeds it,    */
+/* undecided otherwise.                                                     */
+/* ------------------------------------------------------------------------ */
+void ora_estimate_hist(const uint64_t* hist, uint32_t n_bins, uint64_t n, double* H, double* p1,
+                       double* r_lo, double* r_hi, int* predict)
+{
+    uint64_t mx = 0;
+    double h = 0.0;
+    for (uint32_t s = 0; s < n_bins; ++s) {
+        if (!hist[s]) continue;
+        double p = (double)hist[s] / (double)n;
+        h -= p * log2(p);
+        if (hist[s] > mx) mx = hist[s];
+    }
+    double q = (double)mx / (double)n;
+    double lo = 0.0;
+    if (q > 0.4 && q < 1.0) lo = 1.0 - (-q * log2(q) - (1.0 - q) * log2(1.0 - q));
+    else if (q >= 1.0) lo = 1.0; /* a single symbol: one bit per symbol, H = 0 */
+    *H = h;
+    *p1 = q;
+    *r_lo = lo;
+    *r_hi = q + 0.086;
+    if (predict) *predict = h + *r_hi <= 1.09 ? 1 : (h + lo > 1.09 ? 0 : 2);
+}
+
+/* SplitMix64 as a counter-based generator (Steele, Lea, Flood 2014): the    */
+/* k-th output for a seed is the output of a SplitMix64 state that has      */
+/* advanced k+1 times from the seed, i.e. mix(seed + (k+1) * golden gamma). */
+uint64_t ora_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Sampled binary madogram of the quant-codes (Sec. III-B.2): sample k draws */
+/* one 64-bit number; its high half picks a in [0, n) and its low half a    */
+/* distance d in [1, dmax] (both by multiply-shift); a pair whose second    */
+/* element falls outside the field is skipped.  cnt[d] counts the pairs at  */
+/* distance d and sum[d] those whose two codes differ (binary variance).    */
+/* v(d) = sum[d] / cnt[d] is the roughness at d, 1 - v(d) the smoothness.   */
+void ora_madogram(const uint16_t* q, uint64_t n, uint64_t samples, uint64_t seed, uint32_t dmax,
+                  uint64_t* sum, uint64_t* cnt)
+{
+    for (uint32_t d = 0; d <= dmax; ++d) sum[d] = cnt[d] = 0;
+    for (uint64_t k = 0; k < samples; ++k) {
+        uint64_t r = ora_splitmix64(seed, k);
+        uint64_t a = ((r >> 32) * n) >> 32;
+        uint32_t d = 1 + (uint32_t)(((r & 0xFFFFFFFFull) * dmax) >> 32);
+        if (a + d >= n) continue;
+        cnt[d] += 1;
+        sum[d] += q[a] != q[a + d];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Archive format v2 (little-endian, 128-byte header, 16-byte aligned        */
 /* sections, zero padding).                                                  */
 /*   0 "EBC1", 4 version u16 = 2, 6 flags u16 = 0,                           */

@@ -82,6 +82,9 @@ def lib():
             "ora_reconstruct": (None, [P, i32, P, P, P]),
             "ora_dequant": (None, [P, u64, f64, P]),
             "ora_dequant64": (None, [P, u64, f64, P]),
+            "ora_estimate_hist": (None, [P, u32, u64, P, P, P, P, P]),
+            "ora_splitmix64": (u64, [u64, u64]),
+            "ora_madogram": (None, [P, u64, u64, u64, u32, P, P]),
             "ora_compress_bound": (u64, [i32, P, u32, u32]),
             "ora_compress": (i32, [P, i32, i32, P, i32, f64, u32, i32, u32, P, P, u64, P]),
             "ora_decompress": (i32, [P, u64, P, u64]),
@@ -268,6 +271,31 @@ def dequant(d: np.ndarray, ebx2: float, fp64: bool = False) -> np.ndarray:
     out = np.empty(d.shape, dtype=np.float64 if fp64 else np.float32)
     (lib().ora_dequant64 if fp64 else lib().ora_dequant)(_p(d), d.size, float(ebx2), _p(out))
     return out
+
+
+def estimate_hist(hist: np.ndarray, n: int | None = None) -> dict:
+    """Entropy, p1, the redundancy bounds and the predicted workflow
+    (1 run-length, 0 Huffman, 2 undecided) from a histogram."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    n = int(hist.sum()) if n is None else int(n)
+    H, p1, lo, hi, pr = C.c_double(), C.c_double(), C.c_double(), C.c_double(), C.c_int()
+    lib().ora_estimate_hist(_p(hist), hist.size, n, C.byref(H), C.byref(p1), C.byref(lo),
+                            C.byref(hi), C.byref(pr))
+    return dict(entropy=H.value, p1=p1.value, r_lo=lo.value, r_hi=hi.value, predict=pr.value,
+                bits_lo=H.value + lo.value, bits_hi=H.value + hi.value)
+
+
+def splitmix64(seed: int, k: int) -> int:
+    return int(lib().ora_splitmix64(seed, k))
+
+
+def madogram(q: np.ndarray, samples: int, seed: int, dmax: int = 200):
+    """(sum, cnt) per distance 0..dmax of the sampled binary madogram."""
+    q = np.ascontiguousarray(q, dtype=np.uint16).ravel()
+    s = np.zeros(dmax + 1, dtype=np.uint64)
+    c = np.zeros(dmax + 1, dtype=np.uint64)
+    lib().ora_madogram(_p(q), q.size, int(samples), int(seed), dmax, _p(s), _p(c))
+    return s, c
 
 
 # -------------------------------------------------------------- pipeline

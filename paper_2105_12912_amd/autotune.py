@@ -1,12 +1,15 @@
-"""Autotuner for the launch geometry of construction and reconstruction.
+"""Autotuner for the launch geometry: tiles, construction grid, scan schedule.
 
 For each shape class (rank, ceil(log2 nx), size class) present in a set of
 fields, every candidate (workgroup tile width in waves along x, persistent
 construction grid) is installed in the library's tuning table, the class's
 largest field is compressed and decompressed with per-stage event timing, and
-the candidate with the smallest construct + reconstruct time wins.  Every
-candidate's archive must be byte-identical to the first one's and its
-reconstruction bit-identical: tuning is only allowed to change speed.
+the candidate with the smallest construct + reconstruct time wins.  Then the
+scan schedule (tile count up to which a prefix sum adds the preceding tile
+sums directly instead of scanning them first) is chosen the same way from
+the stages made of scans.  Every candidate's archive must be byte-identical
+to the first one's and its reconstruction bit-identical: tuning is only
+allowed to change speed.
 
 The chosen table is installed with ``ebc_set_tuning`` and can be saved to /
 loaded from a JSON cache.
@@ -26,6 +29,10 @@ CANDIDATES = {
 }
 
 
+SCANS = (64, 1024, 16384)
+SCAN_STAGES = ("scan_outliers", "encode_scan", "decode_prep")
+
+
 class TuningChangedBytes(AssertionError):
     pass
 
@@ -37,11 +44,12 @@ def shape_key(x):
     return rank, nxc, nc
 
 
-def _entry(key, wx, grid):
-    return dict(rank=key[0], nx_class=key[1], n_class=key[2], tile_wx=wx, grid=grid)
+def _entry(key, wx, grid, scan=0):
+    return dict(rank=key[0], nx_class=key[1], n_class=key[2], tile_wx=wx, grid=grid,
+                scan_direct=scan)
 
 
-def _time_candidate(x, eb, reps, ws):
+def _time_candidate(x, eb, reps, ws, stages=("construct", "reconstruct")):
     import torch
 
     best = None
@@ -49,7 +57,10 @@ def _time_candidate(x, eb, reps, ws):
     for _ in range(reps):
         a, cs = ebc.compress(x, eb, "rel", stats=True, workspace=ws)
         y, ds = ebc.decompress(a, stats=True, workspace=ws)
-        t = cs.stages().get("construct", 0.0) + ds.stages().get("reconstruct", 0.0)
+        st = dict(cs.stages())
+        for k, v in ds.stages().items():
+            st[k] = st.get(k, 0.0) + v
+        t = sum(st.get(k, 0.0) for k in stages)
         best = t if best is None else min(best, t)
     torch.cuda.synchronize()
     return best, a, y
@@ -87,8 +98,21 @@ def tune(fields, eb: float = 1e-4, reps: int = 2, install: bool = True):
                     raise TuningChangedBytes(f"class {key}: tile {wx} grid {grid} changed the output")
                 times[(wx, grid)] = t
             wx, grid = min(times, key=times.get)
-            table.append(_entry(key, wx, grid))
-            report[str(key)] = {f"{w}x{g}": round(v, 4) for (w, g), v in times.items()}
+            rep = {f"{w}x{g}": round(v, 4) for (w, g), v in times.items()}
+            stimes = {}
+            for scan in SCANS:
+                st = ebc.ebc_set_tuning(table + [_entry(key, wx, grid, scan)])
+                if st != ebc.EBC_OK:
+                    raise ebc.EbcError(st, "ebc_set_tuning")
+                t, a, y = _time_candidate(x, eb, reps, ws, SCAN_STAGES)
+                if not (a.numel() == ref_a.numel() and torch.equal(a, ref_a)
+                        and torch.equal(y.view(torch.int32), ref_y.view(torch.int32))):
+                    raise TuningChangedBytes(f"class {key}: scan schedule {scan} changed the output")
+                stimes[scan] = t
+            scan = min(stimes, key=stimes.get)
+            rep.update({f"scan{k}": round(v, 4) for k, v in stimes.items()})
+            table.append(_entry(key, wx, grid, scan))
+            report[str(key)] = rep
     finally:
         ebc.ebc_set_tuning(table if install else [])
     return table, report

@@ -24,7 +24,8 @@ def _torch():
 
 
 class BatchCompress:
-    """Compress a fixed list of contiguous fp32 CUDA tensors with one parameter set.
+    """Compress a fixed list of contiguous CUDA tensors (all fp32, or all fp64)
+    with one parameter set.
 
     Output buffers (one per field, sized by the compress bound), the result
     records and the workspace are allocated once, here; ``launch`` enqueues
@@ -38,12 +39,13 @@ class BatchCompress:
             raise ValueError("empty batch")
         self.fields = list(fields)
         self.device = self.fields[0].device
-        self.params = ebc.make_params(eb, mode, n_bins, codec, huff_chunk)
+        dt = self.fields[0].dtype
+        self.params = ebc.make_params(eb, mode, n_bins, codec, huff_chunk, ebc._dtype_code(self.fields[0]))
         self.outs = []
         descs = []
         for x in self.fields:
-            if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
-                raise ValueError("fields must be contiguous float32 CUDA tensors")
+            if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
+                raise ValueError("fields must be contiguous CUDA tensors of one float type")
             rank, dims = ebc.field_rank_dims(x)
             bound = ebc.ebc_compress_bound(rank, dims, self.params)
             out = torch.empty(bound, dtype=torch.uint8, device=self.device)
@@ -60,7 +62,7 @@ class BatchCompress:
 
     @property
     def input_bytes(self) -> int:
-        return sum(x.numel() * 4 for x in self.fields)
+        return sum(x.numel() * x.element_size() for x in self.fields)
 
     def launch(self, stream=None):
         st = ebc.ebc_batch_compress_async(self.descs, self.params, self.res.data_ptr(),
@@ -109,7 +111,8 @@ class BatchCompress:
 
 
 class BatchDecompress:
-    """Decompress a fixed list of archives (uint8 CUDA tensors) into fp32 tensors."""
+    """Decompress a fixed list of archives (uint8 CUDA tensors) into tensors of
+    each archive's element type (fp32 or fp64)."""
 
     def __init__(self, archives, outs=None):
         torch = _torch()
@@ -125,8 +128,8 @@ class BatchDecompress:
             info = ebc.ebc_archive_info(self.headers[i])
             nx, ny, nz = info["dims"]
             shape = {1: (nx,), 2: (ny, nx), 3: (nz, ny, nx)}[info["rank"]]
-            out = outs[i] if outs is not None else torch.empty(shape, dtype=torch.float32,
-                                                                 device=self.device)
+            dt = torch.float64 if info["dtype"] == ebc.EBC_F64 else torch.float32
+            out = outs[i] if outs is not None else torch.empty(shape, dtype=dt, device=self.device)
             self.outs.append(out)
             refs.append(ebc.ebc_archive_ref(d_archive=a.data_ptr(), size=a.numel(),
                                             h_header=C.cast(self._hbufs[i], C.c_void_p),
@@ -139,7 +142,7 @@ class BatchDecompress:
 
     @property
     def output_bytes(self) -> int:
-        return sum(o.numel() * 4 for o in self.outs)
+        return sum(o.numel() * o.element_size() for o in self.outs)
 
     def launch(self, stream=None):
         st = ebc.ebc_batch_decompress_async(self.refs, self.status.data_ptr(), self.ws.data_ptr(),

@@ -29,6 +29,7 @@ SOURCES = [
     "k_outlier.hip",
     "k_recon.hip",
     "k_archive.hip",
+    "k_estimate.hip",
     "capi.cpp",  # host code only
 ]
 

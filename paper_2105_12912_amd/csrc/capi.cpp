@@ -84,12 +84,12 @@ void shape_class(int rank, const uint64_t dims[3], uint32_t* nxc, uint32_t* nc)
 }
 
 struct Tune {
-    uint32_t wx, grid;
+    uint32_t wx, grid, scan;
 };
 
 Tune lookup_tune(int rank, const uint64_t dims[3])
 {
-    Tune t = {0, 0};
+    Tune t = {0, 0, 0};
     if (!t_tune) return t;
     uint32_t nxc, nc;
     shape_class(rank, dims, &nxc, &nc);
@@ -97,6 +97,7 @@ Tune lookup_tune(int rank, const uint64_t dims[3])
         if (e.rank == rank && e.nx_class == nxc && e.n_class == nc) {
             t.wx = e.tile_wx;
             t.grid = e.grid;
+            t.scan = e.scan_direct;
         }
     return t;
 }
@@ -106,13 +107,15 @@ struct Params {
     int eb_mode, codec;
     double eb;
     uint32_t n_bins, hc;
+    int dtype;  // 0 fp32, 1 fp64 input
 };
 
 int check_params(const ebc_params* p, Params* out)
 {
     if (!p) return fail(EBC_ERR_ARG, "params is NULL");
     if (p->eb_mode != EBC_EB_ABS && p->eb_mode != EBC_EB_REL) return fail(EBC_ERR_ARG, "bad eb_mode");
-    if (p->codec < EBC_CODEC_AUTO || p->codec > EBC_CODEC_RLE) return fail(EBC_ERR_ARG, "bad codec");
+    if (p->codec < EBC_CODEC_AUTO || p->codec > EBC_CODEC_AUTO_VLE) return fail(EBC_ERR_ARG, "bad codec");
+    if (p->dtype != EBC_F32 && p->dtype != EBC_F64) return fail(EBC_ERR_ARG, "bad data type");
     if (!(p->eb > 0.0) || !std::isfinite(p->eb)) return fail(EBC_ERR_EB, "eb must be finite and > 0");
     if (p->n_bins < 4 || p->n_bins > 65536 || (p->n_bins & 1))
         return fail(EBC_ERR_BINS, "n_bins must be even in [4, 65536]");
@@ -121,12 +124,12 @@ int check_params(const ebc_params* p, Params* out)
         return fail(EBC_ERR_ARG, "huff_chunk must be a power of two in [64, 65536]");
     if (p->n_bins > kMaxBins)
         return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented on this GPU path", kMaxBins);
-    if (hc > kMaxHc) return fail(EBC_ERR_UNSUPPORTED, "huff_chunk > %u not implemented", kMaxHc);
     out->eb_mode = p->eb_mode;
     out->codec = p->codec;
     out->eb = p->eb;
     out->n_bins = p->n_bins;
     out->hc = hc;
+    out->dtype = p->dtype;
     return EBC_OK;
 }
 
@@ -163,6 +166,7 @@ struct Geo {
     uint64_t nx, ny, nz, n;
     uint32_t wx, xs, nxb, nyb, nzb, n_wave_tiles, wg_tiles;
     uint32_t grid;  // persistent construction grid (workgroups)
+    uint32_t scan;  // scan schedule: direct down-sweep up to this many tiles (0: default)
     uint32_t n_seg, range_units, ow_units, n_hch, hwg_units, hdwg_units, n_rt;
     uint32_t hs, n_sub, hpwg_units;
 };
@@ -176,6 +180,7 @@ Geo make_geo(int rank, const uint64_t dims[3], uint32_t hc)
     const Tune t = lookup_tune(rank, dims);
     g.wx = rank > 1 && t.wx ? t.wx : choose_wx(rank, g.nx);
     g.grid = t.grid;  // 0: as many workgroups as the device holds at once
+    g.scan = t.scan;
     if (rank == 1) {
         g.xs = 256;
         g.nxb = 1, g.nyb = 1, g.nzb = 1;
@@ -225,6 +230,7 @@ struct Batch {
     struct Group {
         int rank;
         bool vec;
+        bool f64;
         int first, count;
         uint32_t wg_tiles;
         uint32_t blocks;  // construction grid
@@ -234,12 +240,14 @@ struct Batch {
              tot_rt = 0, tot_runs = 0, tot_sc = 0, tot_rl = 0, tot_fx = 0, tot_sub = 0, tot_hpwg = 0;
     uint32_t max_rle_units = 0;
     bool overflow = false;  // some work-unit total of the batch reached 2^32
+    uint32_t scan = 0;      // scan schedule of the call (largest tuned value of its fields)
     FieldDesc* d_fd = nullptr;
     FieldDyn* d_dyn = nullptr;
     uint32_t *d_seg = nullptr, *d_wcnt = nullptr, *d_rcnt = nullptr, *d_starts = nullptr,
              *d_tmp = nullptr, *d_soff = nullptr;
     uint8_t* d_tabs = nullptr;
     uint64_t* d_result = nullptr;
+    EstDev* d_est = nullptr;
     uint64_t ws_bytes = 0;
 };
 
@@ -248,19 +256,20 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // Group fields by (rank, vec) and assign every work-unit base.
 // Default persistent construction grid for a (rank, layout) variant: the
 // workgroups the device holds at once, cached per device and bin count.
-uint32_t resident_grid(int rank, bool vec, uint32_t n_bins)
+uint32_t resident_grid(int rank, bool vec, uint32_t n_bins, bool f64)
 {
     static std::mutex mu;
     static std::vector<std::pair<uint64_t, uint32_t>> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    const uint64_t key = ((uint64_t)dev << 32) | ((uint64_t)n_bins << 3) | (uint64_t)(rank * 2 + (vec ? 1 : 0));
+    const uint64_t key = ((uint64_t)dev << 32) | ((uint64_t)n_bins << 4) | (f64 ? 8u : 0u) |
+                         (uint64_t)(rank * 2 + (vec ? 1 : 0));
     {
         std::lock_guard<std::mutex> lk(mu);
         for (const auto& kv : cache)
             if (kv.first == key) return kv.second;
     }
-    uint32_t g = construct_resident_blocks(rank, vec, n_bins);
+    uint32_t g = construct_resident_blocks(rank, vec, n_bins, f64);
     if (g == 0) g = kConstructBlocks;
     std::lock_guard<std::mutex> lk(mu);
     cache.push_back({key, g});
@@ -282,15 +291,15 @@ struct Tot {
     }
 };
 
-void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec, uint32_t n_bins)
+void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>& vec,
+                  const std::vector<int>& dt, uint32_t n_bins)
 {
     const int nf = B.nf;
     std::vector<int> idx(nf);
     for (int i = 0; i < nf; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        const int ka = geo[a].rank * 2 + (vec[a] ? 1 : 0), kb = geo[b].rank * 2 + (vec[b] ? 1 : 0);
-        return ka < kb;
-    });
+    // groups of one (data type, rank, row alignment): one specialised launch each
+    auto key = [&](int i) { return dt[i] * 8 + geo[i].rank * 2 + (vec[i] ? 1 : 0); };
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key(a) < key(b); });
     B.order = idx;
     B.groups.clear();
     B.overflow = false;
@@ -300,8 +309,10 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
     for (int k = 0; k < nf; ++k) {
         const Geo& g = geo[idx[k]];
         const bool v = vec[idx[k]];
-        if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v) {
-            B.groups.push_back({g.rank, v, k, 0, 0, 0});
+        const bool f64 = dt[idx[k]] == 1;
+        if (B.groups.empty() || B.groups.back().rank != g.rank || B.groups.back().vec != v ||
+            B.groups.back().f64 != f64) {
+            B.groups.push_back({g.rank, v, f64, k, 0, 0, 0});
             wg.v = 0;
         }
         Batch::Group& G = B.groups.back();
@@ -325,10 +336,12 @@ void assign_bases(Batch& B, const std::vector<Geo>& geo, const std::vector<bool>
     B.tot_range = (uint32_t)range.v, B.tot_seg = (uint32_t)seg.v, B.tot_ow = (uint32_t)ow.v;
     B.tot_hch = (uint32_t)hch.v, B.tot_hwg = (uint32_t)hwg.v, B.tot_hdwg = (uint32_t)hdwg.v;
     B.tot_rt = (uint32_t)rt.v, B.tot_sub = (uint32_t)sub.v, B.tot_hpwg = (uint32_t)hpwg.v;
+    B.scan = 0;
+    for (int k = 0; k < nf; ++k) B.scan = std::max(B.scan, geo[k].scan);
     for (auto& G : B.groups) {
         uint32_t grid = 0;
         for (int k = G.first; k < G.first + G.count; ++k) grid = std::max(grid, geo[B.order[k]].grid);
-        if (grid == 0) grid = n_bins ? resident_grid(G.rank, G.vec, n_bins) : kConstructBlocks;
+        if (grid == 0) grid = n_bins ? resident_grid(G.rank, G.vec, n_bins, G.f64) : kConstructBlocks;
         G.blocks = std::min(G.wg_tiles, grid);
         for (int k = G.first; k < G.first + G.count; ++k)
             B.fd[k].hrows = std::min(B.fd[k].wg_tiles, G.blocks);
@@ -356,7 +369,7 @@ void recon3_tiles(const Geo& g, uint32_t t[3])
 // Compression plan: geometry, bases and workspace carving (base == nullptr
 // only sizes the workspace).
 struct CompressIn {
-    const float* in;
+    const void* in;
     int rank;
     uint64_t dims[3];
     void* out;
@@ -369,11 +382,12 @@ int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P,
     B.fd.assign(B.nf, FieldDesc{});
     std::vector<Geo> geo(B.nf);
     std::vector<bool> vec(B.nf);
+    std::vector<int> dt(B.nf, P.dtype);
     for (int i = 0; i < B.nf; ++i) {
         geo[i] = make_geo(fin[i].rank, fin[i].dims, P.hc);
         vec[i] = aligned16(fin[i].in) && (fin[i].rank == 1 || geo[i].nx % 4 == 0);
     }
-    assign_bases(B, geo, vec, P.n_bins);
+    assign_bases(B, geo, vec, dt, P.n_bins);
     Bump bp{ws};
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
@@ -383,6 +397,7 @@ int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P,
     const uint32_t big = std::max({B.tot_seg, B.tot_hch, B.tot_rt});
     B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(big));
     B.d_result = bp.take<uint64_t>(16);
+    B.d_est = bp.take<EstDev>(sizeof(EstDev) * B.nf);
     for (int k = 0; k < B.nf; ++k) {
         const int i = B.order[k];
         const Geo& g = geo[i];
@@ -393,7 +408,9 @@ int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P,
         d.eb_mode = P.eb_mode;
         d.codec_req = P.codec;
         d.eb = P.eb;
-        d.in = fin[i].in;
+        d.dtype = P.dtype;
+        d.in = P.dtype == EBC_F32 ? (const float*)fin[i].in : nullptr;
+        d.in64 = P.dtype == EBC_F64 ? (const double*)fin[i].in : nullptr;
         d.arc = (uint8_t*)fin[i].out;
         d.arc_cap = fin[i].cap;
         d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
@@ -403,10 +420,15 @@ int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P,
         d.rstart = (uint32_t*)d.dsc;  // used only after the outliers are written
         d.hist = bp.take<uint32_t>(4ull * P.n_bins);
         d.hpart = bp.take<uint32_t>(4ull * P.n_bins * d.hrows);
-        d.rpart = bp.take<uint32_t>(12ull * g.range_units);
+        d.rpart = bp.take<uint32_t>(24ull * g.range_units);  // room for 64-bit keys
         d.code = bp.take<uint64_t>(8ull * P.n_bins);
         d.len = bp.take<uint8_t>(P.n_bins);
         d.hbits = bp.take<uint32_t>(4ull * g.n_hch);
+        // RLE+VLE requested: the run values (at most N, and the encoder may
+        // read 30 bytes past the stream) and their histogram
+        const bool vle = P.codec == EBC_CODEC_RLE_VLE || P.codec == EBC_CODEC_AUTO_VLE;
+        d.vsym = vle ? bp.take<uint16_t>(2 * g.n + 64) : nullptr;
+        d.vhist = vle ? bp.take<uint32_t>(4ull * P.n_bins) : nullptr;
     }
     B.ws_bytes = bp.off;
     if (B.overflow) return fail(EBC_ERR_DIMS, "batch too large: a work-unit total reaches 2^32");
@@ -467,33 +489,44 @@ int enqueue_compress(Batch& B, const Params& P, hipStream_t s, Timer& T, bool de
     const int nf = B.nf;
     HIP_TRY(upload_descs(B.fd.data(), nf, B.d_fd, s));
     T.mark("range");
-    HIP_TRY(launch_range(B.d_fd, nf, B.tot_range, s));
+    HIP_TRY(launch_range(B.d_fd, nf, B.tot_range, P.dtype == EBC_F64, s));
     T.mark("params");
     HIP_TRY(launch_params(B.d_fd, nf, s));
     T.mark("construct");
     for (const auto& G : B.groups)
-        HIP_TRY(launch_construct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, P.n_bins,
-                                 B.d_seg, s));
+        HIP_TRY(launch_construct(B.d_fd + G.first, G.count, G.rank, G.vec, G.f64, G.wg_tiles, G.blocks,
+                                 P.n_bins, B.d_seg, s));
     T.mark("hist_reduce");
     HIP_TRY(launch_hist_reduce(B.d_fd, nf, P.n_bins, s));
     T.mark("scan_outliers");
-    HIP_TRY(launch_scan(B.d_seg, B.tot_seg, B.d_tmp, s));
+    HIP_TRY(launch_scan(B.d_seg, B.tot_seg, B.d_tmp, s, B.scan));
     if (debug_stop) return EBC_OK;
     T.mark("codebook");
-    HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, s));
+    HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, 0, s));
+    const bool vle = P.codec == EBC_CODEC_RLE_VLE || P.codec == EBC_CODEC_AUTO_VLE;
     T.mark("encode_count");
-    HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, s));
+    HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, 0, s));
     HIP_TRY(launch_rle_count(B.d_fd, nf, B.tot_rt, B.d_rcnt, s));
     T.mark("encode_scan");
-    HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
-    HIP_TRY(launch_scan(B.d_rcnt, B.tot_rt, B.d_tmp, s));
+    HIP_TRY(launch_scan(B.d_rcnt, B.tot_rt, B.d_tmp, s, B.scan));
+    if (vle) {
+        // RLE+VLE fields: the run values become a stream of their own with a
+        // codebook of their own, counted like the codes of a Huffman field
+        T.mark("rle_vle");
+        HIP_TRY(launch_rle_vle_prep(B.d_fd, nf, B.tot_rt, B.d_rcnt, P.n_bins, s));
+        HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, 1, s));
+        HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, 1, s));
+    }
+    HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s, B.scan));
     T.mark("layout");
     HIP_TRY(launch_layout(B.d_fd, nf, B.d_seg, B.d_wcnt, B.d_rcnt, s));
     T.mark("outlier_write");
     HIP_TRY(launch_outlier_write(B.d_fd, nf, B.tot_ow, B.d_seg, s));
     T.mark("encode_write");
     HIP_TRY(launch_huff_write(B.d_fd, nf, B.tot_hwg, P.hc, P.n_bins, B.d_wcnt, s));
-    HIP_TRY(launch_rle_write(B.d_fd, nf, B.tot_rt, B.d_rcnt, s));
+    // run values of RLE fields into the archive, run starts of both run-length
+    // codecs (they overwrite the outlier delta scratch, now written out)
+    HIP_TRY(launch_rle_write(B.d_fd, nf, B.tot_rt, B.d_rcnt, 1 | 4, s));
     HIP_TRY(launch_rle_len(B.d_fd, nf, B.max_rle_units, s));
     T.mark("header");
     HIP_TRY(launch_header(B.d_fd, nf, s));
@@ -620,15 +653,12 @@ int parse_header(const void* h, uint64_t bytes, Header* H)
 
 int header_supported(const Header& H)
 {
-    if (H.dtype != 0) return fail(EBC_ERR_UNSUPPORTED, "fp64 archives are not implemented");
-    if (H.codec == EBC_ARC_RLE_VLE) return fail(EBC_ERR_UNSUPPORTED, "RLE+VLE archives are not implemented");
     if (H.codec == EBC_ARC_CONST) return EBC_OK;
     const uint32_t want[3][3] = {{256, 1, 1}, {16, 16, 1}, {8, 8, 8}};
     for (int k = 0; k < 3; ++k)
         if (H.chunk[k] != want[H.rank - 1][k])
             return fail(EBC_ERR_UNSUPPORTED, "non-default Lorenzo chunk not implemented");
     if (H.n_bins > kMaxBins) return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented", kMaxBins);
-    if (H.hc > kMaxHc) return fail(EBC_ERR_UNSUPPORTED, "huff_chunk > %u not implemented", kMaxHc);
     return EBC_OK;
 }
 
@@ -636,7 +666,7 @@ struct DecompressIn {
     Header H;
     const void* arc;
     uint64_t size;
-    float* out;
+    void* out;  // elements of the archive's data type
     uint64_t out_elems;
 };
 
@@ -646,12 +676,14 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
     B.fd.assign(B.nf, FieldDesc{});
     std::vector<Geo> geo(B.nf);
     std::vector<bool> vec(B.nf);
+    std::vector<int> dt(B.nf);
     for (int i = 0; i < B.nf; ++i) {
         const Header& H = din[i].H;
         geo[i] = make_geo(H.rank, H.dims, H.hc);
         vec[i] = aligned16(din[i].out) && (H.rank == 1 || geo[i].nx % 4 == 0);
+        dt[i] = H.dtype;
     }
-    assign_bases(B, geo, vec, 0);  // no construction grid needed
+    assign_bases(B, geo, vec, dt, 0);  // no construction grid needed
     Bump bp{ws};
     B.d_fd = bp.take<FieldDesc>(sizeof(FieldDesc) * B.nf);
     B.d_dyn = bp.take<FieldDyn>(sizeof(FieldDyn) * B.nf);
@@ -665,13 +697,15 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
         FieldDesc& d = B.fd[k];
         const Geo& g = geo[B.order[k]];
         d.codec_hdr = H.codec;
-        const bool huff = H.codec == EBC_ARC_HUFFMAN, rle = H.codec == EBC_ARC_RLE,
-                   cst = H.codec == EBC_ARC_CONST;
-        d.n_hch = huff ? g.n_hch : 0, d.hch_base = hch.add(d.n_hch);
-        d.hdwg_units = huff ? g.hdwg_units : 0, d.hdwg_base = hdwg.add(d.hdwg_units);
+        const bool huff = huff_codec(H.codec), rle = rle_codec(H.codec), cst = H.codec == EBC_ARC_CONST;
+        // the Huffman stream: the N codes, or the run values of RLE+VLE
+        const uint64_t hm = H.codec == EBC_ARC_RLE_VLE ? H.n_a : g.n;
+        d.hn = huff ? hm : 0;
         d.hs = g.hs;
-        d.n_sub = huff ? g.n_sub : 0, d.sub_base = sub.add(d.n_sub);
-        d.hpwg_units = huff ? g.hpwg_units : 0, d.hpwg_base = hpwg.add(d.hpwg_units);
+        d.n_hch = huff ? cdiv(hm, H.hc) : 0, d.hch_base = hch.add(d.n_hch);
+        d.n_sub = huff ? cdiv(hm, g.hs) : 0, d.sub_base = sub.add(d.n_sub);
+        d.hdwg_units = cdiv(d.n_sub, kDecLanes), d.hdwg_base = hdwg.add(d.hdwg_units);
+        d.hpwg_units = cdiv(d.n_hch, kBlock), d.hpwg_base = hpwg.add(d.hpwg_units);
         d.n_rt = rle ? g.n_rt : 0, d.rt_base = rt.add(d.n_rt);
         d.n_runs_hdr = rle ? (uint32_t)H.n_a : 0, d.rle_base = runs.add(d.n_runs_hdr);
         d.rl_units = cdiv(d.n_runs_hdr, kBlock), d.rl_base = rl.add(d.rl_units);
@@ -729,7 +763,8 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
         d.hc = H.hc;
         d.eb_mode = H.eb_mode;
         d.eb = H.eb;
-        d.outf = D.out;
+        d.outf = H.dtype == 0 ? (float*)D.out : nullptr;
+        d.outd = H.dtype == 1 ? (double*)D.out : nullptr;
         d.arc = (uint8_t*)D.arc;
         d.arc_cap = D.size;
         d.dyn = B.d_dyn ? B.d_dyn + k : nullptr;
@@ -744,6 +779,11 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
         const bool cst = H.codec == EBC_ARC_CONST;
         d.q = bp.take<uint16_t>(cst ? 0 : 2 * g.n);
         d.dsc = bp.take<int32_t>(cst ? 0 : 4 * g.n);
+        // RLE+VLE: the decoded run values feed the run expansion
+        d.vsym = bp.take<uint16_t>(H.codec == EBC_ARC_RLE_VLE ? 2 * H.n_a : 0);
+        d.hsym = H.codec == EBC_ARC_RLE_VLE ? d.vsym : d.q;
+        d.rval = H.codec == EBC_ARC_RLE_VLE ? d.vsym
+                 : (d.arc ? (const uint16_t*)(d.arc + H.off_val) : nullptr);
         d.sink = bp.take<float>(256);
         const bool r3 = g.rank == 3 && !cst;
         d.oflag = bp.take<uint32_t>(r3 ? 4ull * d.nxb * d.nyb * kWavesPerBlock * d.nzb : 0);
@@ -765,13 +805,15 @@ int enqueue_reconstruct(Batch& B, hipStream_t s, Timer& T)
     if (has3) T.mark("reconstruct");
     for (const auto& G : B.groups)
         if (G.rank == 3)
-            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.f64, G.wg_tiles,
+                                       G.blocks, s));
     if (B.tot_sc) T.mark("outlier_scatter");
     HIP_TRY(launch_outlier_scatter(B.d_fd, B.nf, B.tot_sc, s));
     if (has12) T.mark(has3 ? "reconstruct_12" : "reconstruct");
     for (const auto& G : B.groups)
         if (G.rank != 3)
-            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.wg_tiles, G.blocks, s));
+            HIP_TRY(launch_reconstruct(B.d_fd + G.first, G.count, G.rank, G.vec, G.f64, G.wg_tiles,
+                                       G.blocks, s));
     if (B.tot_fx) T.mark("outlier_fix");
     HIP_TRY(launch_recon_fix(B.d_fd, B.nf, B.tot_fx, s));
     return EBC_OK;
@@ -785,7 +827,7 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     T.mark("decode_prep");
     if (B.tot_hch) {
         HIP_TRY(launch_huff_prep(B.d_fd, nf, B.tot_hpwg, B.d_wcnt, B.d_soff, s));
-        HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s));
+        HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s, B.scan));
         HIP_TRY(launch_words_check(B.d_fd, nf, B.d_wcnt, s));
         T.mark("dectab");
         HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, s));
@@ -794,7 +836,7 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
     }
     if (B.tot_runs) {
         T.mark("rle_decode");
-        HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmp, B.tot_runs, s));
+        HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmp, B.tot_runs, B.scan, s));
     }
     const int st = enqueue_reconstruct(B, s, T);
     if (st) return st;
@@ -883,6 +925,8 @@ int ebc_set_tuning(const ebc_tuning_entry* entries, int n)
             return fail(EBC_ERR_ARG, "tuning entry %d: tile_wx must be 0, 1, 2 or 4", i);
         if (e.grid != 0 && (e.grid < 64 || e.grid > 16384))
             return fail(EBC_ERR_ARG, "tuning entry %d: grid must be 0 or in [64, 16384]", i);
+        if (e.scan_direct > (1u << 20))
+            return fail(EBC_ERR_ARG, "tuning entry %d: scan_direct must be at most 2^20", i);
         t->push_back(e);
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -964,7 +1008,7 @@ int ebc_compress_workspace_size(int rank, const uint64_t dims[3], const ebc_para
     return EBC_OK;
 }
 
-int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+int ebc_compress(const void* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
                  void* d_out, uint64_t out_cap, uint64_t* out_size, void* d_ws, uint64_t ws_bytes,
                  void* stream, ebc_stats* stats)
 {
@@ -983,18 +1027,26 @@ int ebc_compress(const float* d_field, int rank, const uint64_t dims[3], const e
     st = enqueue_compress(B, P, s, T);
     if (st) return st;
     T.mark("end");
+    if (stats) HIP_TRY(launch_estimate(B.d_fd, 1, B.d_est, 0, 0, s));  // after the timed stages
     std::vector<FieldDyn> dyn;
     st = read_dyn(B, dyn, s);
     if (st) return st;
     T.finish();
     fill_stats(stats, dyn[0], B.fd[0].n);
+    if (stats && dyn[0].status == ST_OK && dyn[0].codec != ARC_CONST) {
+        EstDev e;
+        st = read_small(&e, B.d_est, sizeof(EstDev), s);
+        if (st) return st;
+        stats->entropy = e.entropy, stats->p1 = e.p1, stats->r_lo = e.r_lo, stats->r_hi = e.r_hi;
+        stats->predict = e.predict;
+    }
     st = status_of(dyn[0]);
     if (st) return st;
     *out_size = dyn[0].total;
     return EBC_OK;
 }
 
-int ebc_compress_async(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+int ebc_compress_async(const void* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
                        void* d_out, uint64_t out_cap, uint64_t* d_result, void* d_ws,
                        uint64_t ws_bytes, void* stream)
 {
@@ -1028,6 +1080,8 @@ int ebc_archive_info(const void* h_header, uint64_t header_bytes, int* rank, uin
         p->eb = H.eb;
         p->n_bins = H.n_bins;
         p->huff_chunk = H.hc;
+        p->dtype = H.dtype;
+        p->reserved = 0;
     }
     if (codec) *codec = H.codec;
     if (total_bytes) *total_bytes = H.total;
@@ -1050,7 +1104,7 @@ int ebc_decompress_workspace_size(const void* h_header, uint64_t header_bytes, u
     return EBC_OK;
 }
 
-static int decompress_impl(const Header& H, const void* d_archive, uint64_t size, float* d_out,
+static int decompress_impl(const Header& H, const void* d_archive, uint64_t size, void* d_out,
                            uint64_t out_elems, void* d_ws, uint64_t ws_bytes, hipStream_t s,
                            Batch& B, Timer& T)
 {
@@ -1072,7 +1126,7 @@ static int decompress_impl(const Header& H, const void* d_archive, uint64_t size
     return enqueue_decompress(B, s, T);
 }
 
-int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t out_elems,
+int ebc_decompress(const void* d_archive, uint64_t size, void* d_out, uint64_t out_elems,
                    void* d_ws, uint64_t ws_bytes, void* stream, ebc_stats* stats)
 {
     TuneScope tune_scope;
@@ -1107,7 +1161,7 @@ int ebc_decompress(const void* d_archive, uint64_t size, float* d_out, uint64_t 
     return status_of(dyn[0]);
 }
 
-int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t size, float* d_out,
+int ebc_decompress_async(const void* h_header, const void* d_archive, uint64_t size, void* d_out,
                          uint64_t out_elems, void* d_ws, uint64_t ws_bytes, int32_t* d_status,
                          void* stream)
 {
@@ -1288,8 +1342,51 @@ int ebc_batch_decompress_async(int n, const ebc_archive_ref* refs, int32_t* d_st
     return EBC_OK;
 }
 
+// ------------------------------------------------------------------ estimates
+int ebc_estimate(const void* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+                 uint64_t samples, uint64_t seed, ebc_estimates* out, void* d_ws, uint64_t ws_bytes,
+                 void* stream)
+{
+    TuneScope tune_scope;
+    if (!out || !dims) return fail(EBC_ERR_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<CompressIn> fin(1);
+    fin[0] = {d_field, rank, {dims[0], dims[1], dims[2]}, (void*)d_ws, ~0ull};
+    Batch B;
+    Params P;
+    int st = compress_common(fin, p, d_ws, ws_bytes, s, B, P);
+    if (st) return st;
+    Timer T(nullptr, s);
+    st = enqueue_compress(B, P, s, T, true);  // up to the code histogram
+    if (st) return st;
+    HIP_TRY(launch_estimate(B.d_fd, 1, B.d_est, samples, seed, s));
+    std::vector<FieldDyn> dyn;
+    st = read_dyn(B, dyn, s);
+    if (st) return st;
+    st = status_of(dyn[0]);
+    if (st) return st;
+    if (dyn[0].codec == ARC_CONST) return fail(EBC_ERR_ARG, "constant field: no quant-codes");
+    EstDev e;
+    st = read_small(&e, B.d_est, sizeof(EstDev), s);
+    if (st) return st;
+    memset(out, 0, sizeof(*out));
+    out->codec_hint = e.predict;
+    out->entropy = e.entropy, out->p1 = e.p1, out->r_lo = e.r_lo, out->r_hi = e.r_hi;
+    out->bits_lo = e.entropy + e.r_lo, out->bits_hi = e.entropy + e.r_hi;
+    out->hist_max = e.hist_max;
+    out->n_elems = B.fd[0].n;
+    out->samples = samples;
+    uint64_t ts = 0, tc = 0;
+    for (uint32_t d = 0; d <= kMadoDist; ++d) {
+        out->mado_sum[d] = e.mado_sum[d], out->mado_cnt[d] = e.mado_cnt[d];
+        ts += e.mado_sum[d], tc += e.mado_cnt[d];
+    }
+    out->roughness = tc ? (double)ts / (double)tc : 0.0;
+    return EBC_OK;
+}
+
 // ------------------------------------------------------------------ debug
-int ebc_debug_construct(const float* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
+int ebc_debug_construct(const void* d_field, int rank, const uint64_t dims[3], const ebc_params* p,
                         uint16_t* d_q, uint32_t* d_hist, uint32_t* d_oidx, int32_t* d_oval,
                         uint64_t* n_outliers, double* ebx2, void* d_ws, uint64_t ws_bytes,
                         void* stream)

@@ -21,25 +21,32 @@ struct DescBlob {
 
 // scan
 uint32_t scan_tmp_words(uint32_t n);
-hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s);
+// exclusive scan, total in a[n]; direct_max: tile count up to which each
+// tile's workgroup adds the sums of the tiles before it (0: the default),
+// above which the tile sums are scanned by one workgroup first
+hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s, uint32_t direct_max = 0);
 
 // quantisation
-hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
+hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, bool f64, hipStream_t s);
 hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s);
-uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins);
-hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins, bool f64);
+hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, bool f64, uint32_t wg_tiles,
                             uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s);
 hipError_t launch_hist_reduce(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s);
 
 // codebook
 size_t codebook_lds_bytes(uint32_t n_bins);
-hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s);
+hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, int pass, hipStream_t s);
 hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, hipStream_t s);
+
+// compressibility estimates (histogram bounds; madogram over `samples` pairs)
+hipError_t launch_estimate(const FieldDesc* F, int nf, EstDev* est, uint64_t samples, uint64_t seed,
+                           hipStream_t s);
 
 // Huffman
 size_t huff_write_lds_bytes(uint32_t n_bins, uint32_t hc);
 hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t* wcnt,
-                            hipStream_t s);
+                            int which, hipStream_t s);
 hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_t hc,
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s);
 hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, hipStream_t s);
@@ -51,11 +58,17 @@ hipError_t launch_huff_decode(const FieldDesc* F, int nf, uint32_t units, const 
 
 // RLE
 hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t* rcnt, hipStream_t s);
-hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff,
+// what: 1 run values into the archive (RLE), 2 run values into the value
+// stream (RLE+VLE), 4 run starts
+hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff, int what,
                             hipStream_t s);
+// RLE+VLE: run counts, the run-value stream and its histogram
+hipError_t launch_rle_vle_prep(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff,
+                               uint32_t n_bins, hipStream_t s);
 hipError_t launch_rle_len(const FieldDesc* F, int nf, uint32_t max_units, hipStream_t s);
 hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint32_t rt_units,
-                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, hipStream_t s);
+                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, uint32_t scan_direct,
+                             hipStream_t s);
 
 // outliers
 uint32_t outlier_write_units(uint32_t n_seg);
@@ -64,8 +77,7 @@ hipError_t launch_outlier_write(const FieldDesc* F, int nf, uint32_t units, cons
 hipError_t launch_outlier_scatter(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 
 // reconstruction
-uint32_t reconstruct_resident_blocks(int rank, bool vec);
-hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, bool f64, uint32_t wg_tiles,
                               uint32_t blocks, hipStream_t s);
 hipError_t launch_recon_fix(const FieldDesc* F, int nf, uint32_t units, hipStream_t s);
 hipError_t launch_recon_check(const FieldDesc* F, int nf, hipStream_t s);

@@ -26,7 +26,7 @@ constexpr int kBlock = 256;                 // threads per workgroup everywhere
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kHdr = 128;              // archive header bytes
 constexpr uint32_t kMaxBins = 4096;         // n_bins this GPU path implements
-constexpr uint32_t kMaxHc = 4096;           // Huffman chunk symbols implemented
+constexpr uint32_t kPassHc = 4096;          // Huffman chunk symbols an encode pass covers
 constexpr uint32_t kRangeUnit = 16384;      // elements per value-range work unit
 constexpr uint32_t kRleTile = 4096;         // elements per RLE work unit
 constexpr uint32_t kPersistentBlocks = 1024; // grid size of the persistent (grid-stride) kernels
@@ -38,8 +38,14 @@ constexpr uint32_t kL2MaxBits = 8;         // bits a second-level table resolves
 constexpr uint32_t kSubMax = 256;          // Huffman sub-chunk symbols (hs = min(hc, kSubMax))
 constexpr uint32_t kDecLanes = 768;        // decode workgroup: one lane per sub-chunk
 
-enum : int32_t { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2 };
-enum : int32_t { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2 };
+enum : int32_t { ARC_HUFFMAN = 0, ARC_RLE = 1, ARC_CONST = 2, ARC_RLE_VLE = 3 };
+enum : int32_t { REQ_AUTO = 0, REQ_HUFFMAN = 1, REQ_RLE = 2, REQ_RLE_VLE = 3, REQ_AUTO_VLE = 4 };
+
+// A field's symbols go through the Huffman coder: its quant-codes (Huffman
+// codec) or its run values (RLE+VLE codec).
+__host__ __device__ inline bool huff_codec(int32_t c) { return c == ARC_HUFFMAN || c == ARC_RLE_VLE; }
+// A field is run-length coded (with or without a Huffman pass over the values).
+__host__ __device__ inline bool rle_codec(int32_t c) { return c == ARC_RLE || c == ARC_RLE_VLE; }
 enum : int32_t { MODE_ABS = 0, MODE_REL = 1 };
 enum : int32_t {
     ST_OK = 0,
@@ -55,7 +61,7 @@ enum : int32_t {
 struct FieldDyn {
     int32_t status;
     int32_t codec;
-    float mn, mx;
+    double mn, mx;
     double eb_abs, ebx2, inv;
     uint64_t n_out;
     uint64_t n_runs;
@@ -91,8 +97,10 @@ struct FieldDesc {
     uint32_t vec;            // 1: rows 16-byte aligned, quads never straddle rows
     uint32_t slot;           // position of this field in the caller's arrays
     // buffers (device)
-    const EBC_G float* in;   // compress input
-    EBC_G float* outf;       // decompress output
+    const EBC_G float* in;   // compress input (fp32 field)
+    const EBC_G double* in64;  // compress input (fp64 field)
+    EBC_G float* outf;       // decompress output (fp32 archive)
+    EBC_G double* outd;      // decompress output (fp64 archive)
     EBC_G float* sink;       // decompress: 256 bytes that absorb stores of absent elements
     EBC_G uint8_t* arc;      // archive (compress output / decompress input)
     uint64_t arc_cap;        // compress: capacity; decompress: archive size
@@ -101,11 +109,16 @@ struct FieldDesc {
     EBC_G uint32_t* hist;    // n_bins
     EBC_G uint32_t* hpart;   // hrows * n_bins partial histograms
     uint32_t hrows;          // construction workgroups visiting this field
-    EBC_G uint32_t* rpart;   // range partials: 3 words per range unit
+    EBC_G uint32_t* rpart;   // range partials: 3 words per range unit (3 x 64 bits for fp64)
     EBC_G uint64_t* code;    // n_bins packed codewords: (len << 56) | code
     EBC_G uint8_t* len;      // n_bins code lengths
     EBC_G uint32_t* hbits;   // per Huffman chunk bit counts
     EBC_G uint32_t* rstart;  // RLE run starts (compress scratch)
+    EBC_G uint16_t* vsym;    // RLE+VLE: run values (compress: source of the Huffman pass;
+                             // decompress: its output), n entries at most
+    EBC_G uint32_t* vhist;   // RLE+VLE compress: histogram of the run values (n_bins)
+    EBC_G uint16_t* hsym;    // decompress: Huffman decoder output (q, or vsym for RLE+VLE)
+    const EBC_G uint16_t* rval;  // decompress: run values (archive section, or vsym)
     EBC_G uint32_t* oflag;   // decompress 3D: per wave block, a bit per 8-wide x chunk with outliers
     EBC_G uint32_t* fixl;    // decompress 3D: an outlier index in each flagged chunk (n_out)
     EBC_G FieldDyn* dyn;
@@ -126,13 +139,25 @@ struct FieldDesc {
     uint32_t rl_units, rl_base;        // decompress run-length prep: 256 runs per WG
     uint32_t fx_units, fx_base;        // decompress 3D outlier fix-up: 4 chunks per WG
     // decompress: header values
+    uint64_t hn;             // symbols of the Huffman stream (N, or the run count for RLE+VLE)
     uint64_t n_out_hdr;
     uint64_t n_words_hdr;
     double ebx2_hdr;
     double cval;
     int32_t codec_hdr;
-    int32_t dtype;
+    int32_t dtype;           // 0 fp32, 1 fp64 (input at compression, output at decompression)
     uint64_t off_sbits, off_words, off_val, off_rlen, off_oidx, off_oval;
+};
+
+// Compressibility estimates of one field (Sec. III-B), written on the device.
+constexpr uint32_t kMadoDist = 200;        // largest madogram distance (Sec. III-B.2)
+struct EstDev {
+    double entropy, p1, r_lo, r_hi;
+    uint64_t hist_max;
+    int32_t predict;  // 1 run-length, 0 Huffman, 2 undecided
+    int32_t pad;
+    uint64_t mado_sum[kMadoDist + 1];
+    uint64_t mado_cnt[kMadoDist + 1];
 };
 
 // Canonical Huffman decoder tables of one field (built by k_dectab).
@@ -158,7 +183,9 @@ struct DecTab {
     uint16_t perm[kMaxBins];  // symbols ordered by (length, symbol)
 };
 
-__host__ __device__ constexpr uint32_t huff_cpw(uint32_t hc) { return hc <= 1024 ? 4 : 4096 / hc; }
+// chunks per encode workgroup (one per wave); chunks longer than kPassHc
+// symbols are encoded by one wave in passes of kPassHc
+__host__ __device__ constexpr uint32_t huff_cpw(uint32_t hc) { return hc <= 1024 ? 4 : hc <= kPassHc ? kPassHc / hc : 1; }
 
 __host__ __device__ constexpr size_t dectab_bytes() { return (sizeof(DecTab) + 255) & ~(size_t)255; }
 

@@ -7,7 +7,9 @@
 //            symbols; chunks of hc symbols start on a word, their sub-chunks
 //            follow each other without padding)
 //   RLE:     u16 val[n_runs] | u32 len[n_runs]
-//   both:    u32 outlier_index[n_out] | i32 outlier_delta[n_out]
+//   RLE+VLE: u8 len[n_bins] | u16 sbits | u32 words (the run values as a
+//            Huffman stream of their own) | u32 rlen[n_runs]
+//   all:     u32 outlier_index[n_out] | i32 outlier_delta[n_out]
 // The paper leaves the container unspecified; the header records everything
 // a decoder needs (dims, chunking, codec, step, section counts).
 #include "ebc_dev.h"
@@ -39,6 +41,17 @@ __global__ void k_layout(const FieldDesc* __restrict__ F, int nf, const uint32_t
         dy->off_sbits = align16(kHdr + fd.n_bins);
         dy->off_words = align16(dy->off_sbits + 2ull * fd.n_sub);
         off_o = align16(dy->off_words + 4ull * nw);
+    } else if (dy->codec == ARC_RLE_VLE) {
+        // the Huffman stream of the R run values, then the run lengths
+        const uint64_t R = roff[fd.rt_base + fd.n_rt] - roff[fd.rt_base];
+        const uint64_t nch = (R + fd.hc - 1) / fd.hc, nsub = (R + fd.hs - 1) / fd.hs;
+        const uint64_t nw = woff[fd.hch_base + nch] - woff[fd.hch_base];
+        dy->n_runs = R;
+        dy->n_words = nw;
+        dy->off_sbits = align16(kHdr + fd.n_bins);
+        dy->off_words = align16(dy->off_sbits + 2ull * nsub);
+        dy->off_rlen = align16(dy->off_words + 4ull * nw);
+        off_o = align16(dy->off_rlen + 4ull * R);
     } else {
         const uint64_t R = roff[fd.rt_base + fd.n_rt] - roff[fd.rt_base];
         dy->n_runs = R;
@@ -96,26 +109,34 @@ __global__ void k_header(const FieldDesc* __restrict__ F, int nf)
         const uint64_t cb = dy->codec == ARC_CONST ? (uint64_t)__double_as_longlong((double)dy->mn) : 0ull;
         h[20] = (uint32_t)cb;
         h[21] = (uint32_t)(cb >> 32);
-        const uint64_t na = dy->codec == ARC_HUFFMAN ? (uint64_t)fd.n_hch : dy->n_runs;
+        const uint64_t na = dy->codec == ARC_HUFFMAN ? (uint64_t)fd.n_hch : dy->n_runs;  // RLE, RLE+VLE: runs
         const uint64_t v[4] = {dy->codec == ARC_CONST ? 0ull : dy->n_out,
                                dy->codec == ARC_CONST ? 0ull : na, dy->n_words, dy->total};
         for (int k = 0; k < 4; ++k) {
             h[22 + 2 * k] = (uint32_t)v[k];
             h[23 + 2 * k] = (uint32_t)(v[k] >> 32);
         }
-        h[30] = dy->codec == ARC_HUFFMAN ? fd.hs : 0u;
+        h[30] = huff_codec(dy->codec) ? fd.hs : 0u;
         h[31] = 0;
     }
     __syncthreads();
     if (l < 32) ((EBC_G uint32_t*)a)[l] = h[l];
     if (dy->codec == ARC_CONST) return;
     const uint64_t no = dy->n_out;
-    if (dy->codec == ARC_HUFFMAN) {
+    if (huff_codec(dy->codec)) {
+        const bool vle = dy->codec == ARC_RLE_VLE;
+        const uint64_t nsub = vle ? (dy->n_runs + fd.hs - 1) / fd.hs : fd.n_sub;
 #pragma unroll 8
         for (uint32_t s = l; s < fd.n_bins; s += kWave) a[kHdr + s] = fd.len[s];
         zero_gap(a, kHdr + fd.n_bins, dy->off_sbits, l);
-        zero_gap(a, dy->off_sbits + 2ull * fd.n_sub, dy->off_words, l);
-        zero_gap(a, dy->off_words + 4ull * dy->n_words, dy->off_oidx, l);
+        zero_gap(a, dy->off_sbits + 2ull * nsub, dy->off_words, l);
+        const uint64_t words_end = dy->off_words + 4ull * dy->n_words;
+        if (vle) {
+            zero_gap(a, words_end, dy->off_rlen, l);
+            zero_gap(a, dy->off_rlen + 4ull * dy->n_runs, dy->off_oidx, l);
+        } else {
+            zero_gap(a, words_end, dy->off_oidx, l);
+        }
     } else {
         zero_gap(a, kHdr + 2ull * dy->n_runs, dy->off_rlen, l);
         zero_gap(a, dy->off_rlen + 4ull * dy->n_runs, dy->off_oidx, l);

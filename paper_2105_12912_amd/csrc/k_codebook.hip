@@ -83,11 +83,16 @@ __device__ void canonical_rank(const uint8_t* len_s, uint32_t nb, uint16_t* cnt,
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ F)
+// pass 0: the codebook of the quant-codes and the codec decision; pass 1
+// (RLE+VLE fields only): the codebook of the run values, from their own
+// histogram, which replaces the first in code / len.
+__global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ F, int pass)
 {
     const FieldDesc& fd = F[blockIdx.x];
     EBC_G FieldDyn* dy = fd.dyn;
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
+    if (pass == 1 && dy->codec != ARC_RLE_VLE) return;
+    const EBC_G uint32_t* __restrict__ hist = pass == 0 ? fd.hist : fd.vhist;
     const uint32_t nb = fd.n_bins;
     const uint32_t P = pow2ceil(nb);
     const uint32_t Pa = max(P, 512u);
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
     // leaves: key = (freq << 16) | symbol; absent symbols sort last
     uint32_t used = 0;
     for (uint32_t s = threadIdx.x; s < P; s += kCb) {
-        const uint32_t h = s < nb ? fd.hist[s] : 0u;
+        const uint32_t h = s < nb ? hist[s] : 0u;
         keys[s] = h ? (((uint64_t)h << 16) | s) : ~0ull;
         used += h != 0;
     }
@@ -328,7 +333,7 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
             if (L) {
                 const uint64_t code = first[L] + cnt[b * 65 + L] + rank[k];
                 packed = ((uint64_t)L << 56) | code;
-                bits += (uint64_t)fd.hist[s] * L;
+                bits += (uint64_t)hist[s] * L;
             }
             fd.code[s] = packed;
             fd.len[s] = (uint8_t)L;
@@ -338,13 +343,21 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
     __shared__ uint64_t s_bits[kCbWaves];
     if (l == 0) s_bits[w] = bits;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && pass == 0) {
         uint64_t tb = 0;
         for (int k = 0; k < kCbWaves; ++k) tb += s_bits[k];
         dy->huff_bits = tb;
+        // the 1.09-bit rule picks the run-length workflow; with VLE requested
+        // its run values are Huffman-coded as well
+        const bool rle = 100ull * tb <= 109ull * fd.n;
         int codec;
-        if (fd.codec_req == REQ_AUTO) codec = 100ull * tb <= 109ull * fd.n ? ARC_RLE : ARC_HUFFMAN;
-        else codec = fd.codec_req == REQ_RLE ? ARC_RLE : ARC_HUFFMAN;
+        switch (fd.codec_req) {
+        case REQ_AUTO: codec = rle ? ARC_RLE : ARC_HUFFMAN; break;
+        case REQ_AUTO_VLE: codec = rle ? ARC_RLE_VLE : ARC_HUFFMAN; break;
+        case REQ_HUFFMAN: codec = ARC_HUFFMAN; break;
+        case REQ_RLE: codec = ARC_RLE; break;
+        default: codec = ARC_RLE_VLE; break;
+        }
         dy->codec = codec;
         dy->n_out = fd.hist[0];
     }
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
 {
     const FieldDesc& fd = F[blockIdx.x];
     EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
+    if (dy->status != ST_OK || !huff_codec(dy->codec)) return;
     DecTab* T = (DecTab*)(tabs + (size_t)blockIdx.x * dectab_bytes());
     const uint32_t nb = fd.n_bins;
     __shared__ uint8_t len_s[kMaxBins];
@@ -531,9 +544,9 @@ __global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
     }
 }
 
-hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s)
+hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, int pass, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kCb), codebook_lds_bytes(n_bins), s, F);
+    hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kCb), codebook_lds_bytes(n_bins), s, F, pass);
     return hipGetLastError();
 }
 

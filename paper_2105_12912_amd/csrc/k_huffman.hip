@@ -21,7 +21,10 @@ namespace ebc {
 
 size_t huff_write_lds_bytes(uint32_t n_bins, uint32_t hc)
 {
-    return (size_t)n_bins * 8 + (size_t)huff_cpw(hc) * 2 * hc * 4;
+    // code table, then per wave a word buffer of 2 * hc words (one pass of
+    // kPassHc symbols for longer chunks)
+    const uint32_t span = hc <= kPassHc ? hc : kPassHc;
+    return (size_t)n_bins * 8 + (size_t)huff_cpw(hc) * 2 * span * 4;
 }
 
 // Symbols [lo, lo + S) of a chunk (S = hc / 64, owned by one lane), kept as
@@ -60,44 +63,57 @@ __device__ __forceinline__ void load_raw(const EBC_G uint16_t* __restrict__ q, u
     }
 }
 
-// One encode work unit: huff_cpw(hc) chunks, one per wavefront.
+// One encode work unit: huff_cpw(hc) chunks, one per wavefront.  The coded
+// stream is a field's quant-codes (Huffman codec) or its run values (RLE+VLE
+// codec, as many as the run count found on the device); `which` selects the
+// codecs a launch covers: 0 Huffman, 1 RLE+VLE, 2 both.
 struct EncUnit {
     int f;
-    uint32_t c;  // this wave's chunk
-    bool ok;     // field is being Huffman-coded
+    uint32_t c;                      // this wave's chunk
+    bool ok;                         // field is being Huffman-coded by this launch
+    const EBC_G uint16_t* src;       // symbols of the stream
+    uint64_t cnt;                    // symbols in the stream
+    uint32_t nch, nsub;              // its chunks and sub-chunks
 };
 
 template <uint32_t S>
-__device__ __forceinline__ EncUnit enc_unit(const FieldDesc* __restrict__ F, int nf, uint32_t t)
+__device__ __forceinline__ EncUnit enc_unit(const FieldDesc* __restrict__ F, int nf, uint32_t t, int which)
 {
     EncUnit u;
     u.f = find_field<&FieldDesc::hwg_base>(F, nf, t);
     const FieldDesc& fd = F[u.f];
     const auto* dk = kconst(fd.dyn);
-    u.ok = dk->status == ST_OK && dk->codec == ARC_HUFFMAN;
+    const int32_t codec = dk->codec;
+    u.ok = dk->status == ST_OK &&
+           (which == 0 ? codec == ARC_HUFFMAN : which == 1 ? codec == ARC_RLE_VLE : huff_codec(codec));
+    const bool vle = codec == ARC_RLE_VLE;
+    u.src = vle ? fd.vsym : fd.q;
+    u.cnt = vle ? dk->n_runs : fd.n;
+    u.nch = vle ? (uint32_t)((u.cnt + fd.hc - 1) / fd.hc) : fd.n_hch;
+    u.nsub = vle ? (uint32_t)((u.cnt + fd.hs - 1) / fd.hs) : fd.n_sub;
     // blockDim = 64 * cpw; the chunk index is wave-uniform (scalar)
     u.c = (t - fd.hwg_base) * huff_cpw(64 * S) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     return u;
 }
 
 // For S >= 8 the loads are unconditional (a lane with nothing to load reads
-// the start of the code array instead), so every pipeline stage issues the
-// same number of loads and the compiler's wait counts never have to assume a
-// stage without them.  Symbols past the field's end are masked by the users;
-// the tail chunk's last lane may read up to 30 bytes past the code array,
-// which the workspace always follows with the outlier scratch.
+// the start of the stream instead), so every pipeline stage issues the same
+// number of loads and the compiler's wait counts never have to assume a stage
+// without them.  Symbols past the stream's end are masked by the users; the
+// tail chunk's last lane may read up to 30 bytes past the stream, which the
+// workspace always follows with other scratch.
 template <uint32_t S>
 __device__ __forceinline__ void enc_issue(const FieldDesc* __restrict__ F, const EncUnit& u, SymRaw<S>& r)
 {
     const FieldDesc& fd = F[u.f];
     const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)lane_id() * S;
-    const bool live = u.ok && u.c < fd.n_hch && lo < fd.n;
+    const bool live = u.ok && u.c < u.nch && lo < u.cnt;
     if (S >= 8) {
-        const EBC_G uint16_t* p = fd.q + (live ? lo : 0);
+        const EBC_G uint16_t* p = u.src + (live ? lo : 0);
 #pragma unroll
         for (uint32_t k = 0; k < SymRaw<S>::NV; ++k) r.v[k] = *(const EBC_G uint4*)(p + 8 * k);
     } else if (live) {
-        load_raw<S>(fd.q, lo, fd.n, r);
+        load_raw<S>(u.src, lo, u.cnt, r);
     }
 }
 
@@ -107,24 +123,24 @@ __device__ __forceinline__ void enc_issue(const FieldDesc* __restrict__ F, const
 // workgroup uniformly (it may synchronise).
 template <uint32_t S, class Proc>
 __device__ __forceinline__ void enc_pipeline(const FieldDesc* __restrict__ F, int nf, uint32_t units,
-                                             Proc& proc)
+                                             int which, Proc& proc)
 {
     uint32_t t = blockIdx.x;
     if (t >= units) return;
     SymRaw<S> A, B;
-    EncUnit ua = enc_unit<S>(F, nf, t), ub;
+    EncUnit ua = enc_unit<S>(F, nf, t, which), ub;
     enc_issue<S>(F, ua, A);
     for (;;) {
         // the next stage's loads are always issued (a dead unit past the end)
         uint32_t tn = t + gridDim.x;
-        ub = enc_unit<S>(F, nf, tn < units ? tn : t);
+        ub = enc_unit<S>(F, nf, tn < units ? tn : t, which);
         if (tn >= units) ub.ok = false;
         enc_issue<S>(F, ub, B);
         proc(ua, A);
         t = tn;
         if (t >= units) break;
         tn = t + gridDim.x;
-        ua = enc_unit<S>(F, nf, tn < units ? tn : t);
+        ua = enc_unit<S>(F, nf, tn < units ? tn : t, which);
         if (tn >= units) ua.ok = false;
         enc_issue<S>(F, ua, A);
         proc(ub, B);
@@ -152,11 +168,11 @@ struct BitsProc {
             __syncthreads();
             cur = u.f;
         }
-        if (u.c >= fd.n_hch) return;
+        if (u.c >= u.nch) return;
         const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)lane_id() * S;
-        // symbols past the field's end count zero bits; every lookup is
+        // symbols past the stream's end count zero bits; every lookup is
         // issued before any is used
-        const uint32_t m = lo < fd.n ? (uint32_t)min<uint64_t>(S, fd.n - lo) : 0u;
+        const uint32_t m = lo < u.cnt ? (uint32_t)min<uint64_t>(S, u.cnt - lo) : 0u;
         uint32_t bits = 0;
 #pragma unroll
         for (uint32_t k = 0; k < S; ++k) {
@@ -173,11 +189,12 @@ struct BitsProc {
 
 template <uint32_t S>
 __global__ __launch_bounds__(kBlock) void k_huff_bits(const FieldDesc* __restrict__ F, int nf,
-                                                      uint32_t* __restrict__ wcnt, uint32_t units)
+                                                      uint32_t* __restrict__ wcnt, uint32_t units,
+                                                      int which)
 {
     __shared__ uint8_t len_s[kMaxBins];
     BitsProc<S> proc{F, wcnt, len_s, -1};
-    enc_pipeline<S>(F, nf, units, proc);
+    enc_pipeline<S>(F, nf, units, which, proc);
 }
 
 // append the low `take` (<= 32) bits of v to a window that starts on a word
@@ -248,12 +265,12 @@ struct WriteProc {
             __syncthreads();
             cur = u.f;
         }
-        const bool live = u.c < fd.n_hch;
+        const bool live = u.c < u.nch;
         const uint32_t cbits = live ? kconst(fd.hbits)[u.c] : 0u;
         const uint32_t nw = (cbits + 31) / 32;
         const uint64_t lo = (uint64_t)u.c * hc + (uint64_t)lane_id() * S;
-        // symbols past the field's end take the empty entry
-        const uint32_t m = live && lo < fd.n ? (uint32_t)min<uint64_t>(S, fd.n - lo) : 0u;
+        // symbols past the stream's end take the empty entry
+        const uint32_t m = live && lo < u.cnt ? (uint32_t)min<uint64_t>(S, u.cnt - lo) : 0u;
         uint64_t e[kKeep ? S : 1];
         uint32_t mybits = 0, lmax = 0;
 #pragma unroll
@@ -309,7 +326,7 @@ struct WriteProc {
             constexpr uint32_t kLps = kSubMax / S < 64 ? kSubMax / S : 64u;
             const uint32_t hs = fd.hs;
             const uint64_t sub = (uint64_t)u.c * (hc / hs) + lane_id() / kLps;
-            if (lane_id() % kLps == 0 && lo < fd.n && sub < fd.n_sub)
+            if (lane_id() % kLps == 0 && lo < u.cnt && sub < u.nsub)
                 ((EBC_G uint16_t*)(arc + dy->off_sbits))[sub] = (uint16_t)sb;
         }
     }
@@ -322,7 +339,142 @@ __global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restri
 {
     extern __shared__ uint64_t lds64[];
     WriteProc<S> proc{F, woff, lds64, -1};
-    enc_pipeline<S>(F, nf, units, proc);
+    enc_pipeline<S>(F, nf, units, 2, proc);
+}
+
+// ------------------------------------------------ chunks longer than kPassHc
+// One wave per chunk, in passes of kPassHc symbols (64 per lane).  The bit
+// count pass sums code lengths per sub-chunk (4 lanes) and per chunk; the
+// write pass packs each pass into an LDS word buffer starting at the bit
+// offset the previous passes reached (its partial last word carried over as
+// the buffer's first word), copies out the complete words and keeps the
+// partial one for the next pass.
+constexpr uint32_t kPassPerLane = kPassHc / kWave;  // 64 symbols
+static_assert(kSubMax % kPassPerLane == 0, "a sub-chunk is a whole number of lanes");
+
+__device__ __forceinline__ void load_pass(const EncUnit& u, uint64_t lo, uint32_t sym[kPassPerLane])
+{
+    const uint64_t i0 = lo + (uint64_t)lane_id() * kPassPerLane;
+    if (i0 + kPassPerLane <= u.cnt) {
+#pragma unroll
+        for (uint32_t k = 0; k < kPassPerLane / 8; ++k) {
+            const uint4 v = *(const EBC_G uint4*)(u.src + i0 + 8 * k);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) sym[8 * k + 2 * h] = w[h] & 0xFFFF, sym[8 * k + 2 * h + 1] = w[h] >> 16;
+        }
+    } else {
+#pragma unroll
+        for (uint32_t k = 0; k < kPassPerLane; ++k) sym[k] = i0 + k < u.cnt ? u.src[i0 + k] : 0xFFFFFFFFu;
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_huff_bits_long(const FieldDesc* __restrict__ F, int nf,
+                                                          uint32_t* __restrict__ wcnt, uint32_t units,
+                                                          int which)
+{
+    __shared__ uint8_t len_s[kMaxBins];
+    int cur = -1;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const EncUnit u = enc_unit<kPassPerLane>(F, nf, t, which);
+        if (!u.ok) continue;
+        const FieldDesc& fd = F[u.f];
+        if (u.f != cur) {
+            for (uint32_t s = threadIdx.x; s < fd.n_bins; s += kWave) len_s[s] = fd.len[s];
+            cur = u.f;
+        }
+        if (u.c >= u.nch) continue;
+        uint64_t bits = 0;
+        for (uint32_t p = 0; p < fd.hc / kPassHc; ++p) {
+            const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)p * kPassHc;
+            if (lo >= u.cnt) break;
+            uint32_t sym[kPassPerLane];
+            load_pass(u, lo, sym);
+            uint32_t b = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kPassPerLane; ++k) b += sym[k] == 0xFFFFFFFFu ? 0u : len_s[sym[k]];
+            bits += wave_sum_u32(b);
+        }
+        if (lane_id() == 0) {
+            fd.hbits[u.c] = (uint32_t)bits;
+            wcnt[fd.hch_base + u.c] = (uint32_t)((bits + 31) / 32);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWave) void k_huff_write_long(const FieldDesc* __restrict__ F, int nf,
+                                                           const uint32_t* __restrict__ woff,
+                                                           uint32_t units)
+{
+    extern __shared__ uint64_t lds64[];
+    int cur = -1;
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const EncUnit u = enc_unit<kPassPerLane>(F, nf, t, 2);
+        if (!u.ok) continue;
+        const FieldDesc& fd = F[u.f];
+        const auto* dy = kconst(fd.dyn);
+        const uint32_t nb = fd.n_bins;
+        uint64_t* code_s = lds64;
+        uint32_t* wbuf = (uint32_t*)(lds64 + nb);
+        if (u.f != cur) {
+            for (uint32_t s = threadIdx.x; s < nb; s += kWave) code_s[s] = write_entry(fd.code[s]);
+            cur = u.f;
+        }
+        if (u.c >= u.nch) continue;
+        const uint32_t wo = woff[fd.hch_base + u.c] - woff[fd.hch_base];
+        EBC_G uint32_t* dst = (EBC_G uint32_t*)(fd.arc + dy->off_words) + wo;
+        EBC_G uint16_t* sbits = (EBC_G uint16_t*)(fd.arc + dy->off_sbits);
+        uint64_t done = 0;      // bits of the chunk already packed
+        uint32_t carry = 0;     // the partial word at bit (done & ~31)
+        uint32_t words_out = 0; // complete words stored
+        for (uint32_t p = 0; p < fd.hc / kPassHc; ++p) {
+            const uint64_t lo = (uint64_t)u.c * fd.hc + (uint64_t)p * kPassHc;
+            if (lo >= u.cnt) break;
+            uint32_t sym[kPassPerLane];
+            load_pass(u, lo, sym);
+            uint32_t mybits = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kPassPerLane; ++k)
+                mybits += sym[k] == 0xFFFFFFFFu ? 0u : (uint32_t)code_s[sym[k]] & 0xFFu;
+            const uint32_t incl = wave_incl_scan_u32(mybits);
+            const uint32_t pass_bits = (uint32_t)__shfl((int)incl, kWave - 1);
+            // sub-chunk counts: 4 lanes of 64 symbols per 256-symbol sub-chunk
+            constexpr uint32_t kLps = kSubMax / kPassPerLane;
+            const uint32_t sb = (uint32_t)__shfl((int)incl, (int)min<uint32_t>(lane_id() + kLps - 1, 63)) -
+                                (incl - mybits);
+            const uint64_t sub = lo / fd.hs + lane_id() / kLps;
+            const uint64_t l0 = lo + (uint64_t)lane_id() * kPassPerLane;
+            if (lane_id() % kLps == 0 && l0 < u.cnt) sbits[sub] = (uint16_t)sb;
+            // buffer word 0 holds the carried partial word
+            const uint32_t head = (uint32_t)(done & 31);
+            const uint32_t nbw = (head + pass_bits + 31) / 32;
+            for (uint32_t i = lane_id(); i < nbw + 1; i += kWave) wbuf[i] = i == 0 ? carry : 0u;
+            const uint32_t b0 = head + incl - mybits;
+            uint32_t w = b0 >> 5, nacc = b0 & 31;
+            uint64_t acc = 0;
+#pragma unroll
+            for (uint32_t k = 0; k < kPassPerLane; ++k) {
+                if (sym[k] == 0xFFFFFFFFu) continue;
+                const uint64_t v = code_s[sym[k]];
+                const uint32_t L = (uint32_t)v & 0xFFu;
+                if (L <= 32) {
+                    put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), L);
+                } else {
+                    const uint64_t cw = fd.code[sym[k]] & ((1ull << 56) - 1);
+                    put_bits(acc, nacc, w, wbuf, cw >> 32, L - 32);
+                    put_bits(acc, nacc, w, wbuf, cw & 0xFFFFFFFFull, 32);
+                }
+            }
+            if (nacc) atomicOr(&wbuf[w], (uint32_t)(acc >> 32));
+            // complete words leave; the last partial one is carried
+            const uint32_t full = (head + pass_bits) / 32;
+            for (uint32_t i = lane_id(); i < full; i += kWave) dst[words_out + i] = wbuf[i];
+            carry = wbuf[full];  // a wave's LDS accesses complete in order
+            words_out += full;
+            done += pass_bits;
+        }
+        if ((done & 31) && lane_id() == 0) dst[words_out] = carry;
+    }
 }
 
 // ------------------------------------------------------------- decoding
@@ -445,6 +597,7 @@ static_assert(kRefillEvery == kCheckEvery, "refill and flush checks share the st
 
 // One lane per sub-chunk (hs = min(hc, 256) symbols, its bit count and its
 // start from the archive's sub-chunk counts), kDecLanes lanes per workgroup.
+// The decoded stream is the field's quant-codes, or its run values (RLE+VLE).
 // The main loop runs passes of kCheckEvery steps behind one refill point and
 // one flush check.  A step tops the bit buffer up to at least 32 bits
 // (branch-free, with the next stream word read from the ring one step
@@ -470,7 +623,7 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
     const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || dy->codec != ARC_HUFFMAN) return;
+    if (dy->status != ST_OK || !huff_codec(dy->codec)) return;
     const DecTab* __restrict__ T = (const DecTab*)(tabs + (size_t)f * tab_stride);
     for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kDecLanes) lut[i] = T->lut[i];
     const uint32_t l2k = T->l2k, l2n = T->l2n;
@@ -496,14 +649,14 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                                    soff[fd.sub_base + sub]
                              : 0ull;
     const uint64_t lo = (uint64_t)sub * hs;
-    const uint32_t want = live ? (uint32_t)min<uint64_t>(hs, fd.n - lo) : 0u;
+    const uint32_t want = live ? (uint32_t)min<uint64_t>(hs, fd.hn - lo) : 0u;
     const uint32_t w0 = (uint32_t)(b0 >> 5);
     const uint32_t skip = (uint32_t)(b0 & 31);
     const uint32_t nwl = live ? (skip + nbits + 31) / 32 : 0u;  // words the lane may read
     // the chunk words were checked against the archive's word count, and a
     // sub-chunk ends inside its chunk by construction of the offsets
     const EBC_G uint32_t* __restrict__ words = (const EBC_G uint32_t*)(arc + fd.off_words) + w0;
-    EBC_G uint16_t* __restrict__ out = fd.q + lo;
+    EBC_G uint16_t* __restrict__ out = fd.hsym + lo;
     const LongCode lc{maxl, s_endv, s_first, s_off, T->perm};
     uint32_t* row = s_stage + threadIdx.x * kStageWords;
     uint16_t* row16 = (uint16_t*)row;
@@ -585,7 +738,7 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                 if (spL >= kFlush) {
                     const uint32_t* src = wave_rows + L * kStageWords + part * 4;
                     const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
-                    *(EBC_G uint4*)(fd.q + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
+                    *(EBC_G uint4*)(fd.hsym + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
                 }
             }
             if (sp >= kFlush) {
@@ -654,7 +807,7 @@ __global__ __launch_bounds__(kBlock) void k_huff_prep(const FieldDesc* __restric
     const int f = find_field<&FieldDesc::hpwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     const uint32_t c = (t - fd.hpwg_base) * kBlock + threadIdx.x;
-    if (fd.dyn->codec != ARC_HUFFMAN || c >= fd.n_hch) return;
+    if (!huff_codec(fd.dyn->codec) || c >= fd.n_hch) return;
     const uint32_t per = fd.hc / fd.hs;
     const uint32_t s0 = c * per, s1 = min(s0 + per, fd.n_sub);
     const EBC_G uint16_t* sb = (const EBC_G uint16_t*)(fd.arc + fd.off_sbits);
@@ -684,7 +837,7 @@ __global__ void k_words_check(const FieldDesc* __restrict__ F, int nf, const uin
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= nf) return;
     const FieldDesc& fd = F[f];
-    if (fd.codec_hdr != ARC_HUFFMAN) return;
+    if (!huff_codec(fd.codec_hdr)) return;
     const uint32_t tot = woff[fd.hch_base + fd.n_hch] - woff[fd.hch_base];
     if ((uint64_t)tot != fd.n_words_hdr) atomicMin(&fd.dyn->status, (int32_t)ST_ERR_ARCHIVE);
 }
@@ -699,11 +852,16 @@ hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, 
 static uint32_t persistent_grid(uint32_t units) { return units < kPersistentBlocks ? units : kPersistentBlocks; }
 
 hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t* wcnt,
-                            hipStream_t s)
+                            int which, hipStream_t s)
 {
     if (!units) return hipSuccess;
+    if (hc > kPassHc) {
+        hipLaunchKernelGGL(k_huff_bits_long, dim3(persistent_grid(units)), dim3(kWave), 0, s, F, nf, wcnt,
+                           units, which);
+        return hipGetLastError();
+    }
     EBC_HC_DISPATCH(k_huff_bits, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)), 0, s, F, nf,
-                    wcnt, units)
+                    wcnt, units, which)
     return hipGetLastError();
 }
 
@@ -711,6 +869,11 @@ hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s)
 {
     if (!units) return hipSuccess;
+    if (hc > kPassHc) {
+        hipLaunchKernelGGL(k_huff_write_long, dim3(persistent_grid(units)), dim3(kWave),
+                           huff_write_lds_bytes(n_bins, hc), s, F, nf, woff, units);
+        return hipGetLastError();
+    }
     EBC_HC_DISPATCH(k_huff_write, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)),
                     huff_write_lds_bytes(n_bins, hc), s, F, nf, woff, units)
     return hipGetLastError();

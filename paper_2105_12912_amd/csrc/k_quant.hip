@@ -79,6 +79,61 @@ __global__ __launch_bounds__(kBlock) void k_range(const FieldDesc* __restrict__ 
     }
 }
 
+// Value range of an fp64 field: the same ordered-key min / max, with 64-bit
+// keys; the partials take the unit's three 64-bit words (min, max, bad).
+__device__ __forceinline__ uint64_t double_key(double f)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(f);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_double(uint64_t k)
+{
+    const uint64_t b = (k & 0x8000000000000000ull) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+__global__ __launch_bounds__(kBlock) void k_range64(const FieldDesc* __restrict__ F, int nf)
+{
+    const uint32_t u = blockIdx.x;
+    const int f = find_field<&FieldDesc::range_base>(F, nf, u);
+    const FieldDesc& fd = F[f];
+    const uint64_t lo = (uint64_t)(u - fd.range_base) * kRangeUnit;
+    const uint64_t hi = min(lo + (uint64_t)kRangeUnit, fd.n);
+    const EBC_G double* __restrict__ in = fd.in64;
+    uint64_t kmin = ~0ull, kmax = 0ull;
+    uint32_t bad = 0u;
+    for (uint64_t i = lo + 2u * threadIdx.x; i < hi; i += 2u * kBlock) {
+        for (int k = 0; k < 2; ++k) {
+            if (i + k < hi) {
+                const double v = in[i + k];
+                bad |= !isfinite(v);
+                const uint64_t key = double_key(v);
+                kmin = min(kmin, key);
+                kmax = max(kmax, key);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        kmin = min(kmin, (uint64_t)__shfl_xor((long long)kmin, o));
+        kmax = max(kmax, (uint64_t)__shfl_xor((long long)kmax, o));
+        bad |= (uint32_t)__shfl_xor((int)bad, o);
+    }
+    __shared__ uint64_t s_red[3][kWavesPerBlock];
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) s_red[0][w] = kmin, s_red[1][w] = kmax, s_red[2][w] = bad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kWavesPerBlock; ++k) {
+            kmin = min(kmin, s_red[0][k]);
+            kmax = max(kmax, s_red[1][k]);
+            bad |= (uint32_t)s_red[2][k];
+        }
+        EBC_G uint64_t* rp = (EBC_G uint64_t*)fd.rpart + 3ull * (u - fd.range_base);
+        rp[0] = kmin, rp[1] = kmax, rp[2] = bad;
+    }
+}
+
 // ilogb of a positive finite double, exact for subnormals too.
 __device__ __forceinline__ int ilogb_pos(double x)
 {
@@ -103,22 +158,35 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
     const FieldDesc& fd = F[blockIdx.x];
     EBC_G FieldDyn* dy = fd.dyn;
     for (uint32_t b = threadIdx.x; b < fd.n_bins; b += kBlock) fd.hist[b] = 0;
-    uint32_t kmin = 0xFFFFFFFFu, kmax = 0u, bad = 0u;
+    const bool f64 = fd.dtype == 1;
+    // keys widened to 64 bits (fp32 keys sit in the low word)
+    uint64_t kmin = ~0ull, kmax = 0ull;
+    uint32_t bad = 0u;
     // several partials in flight per wait
+    if (f64) {
 #pragma unroll 8
-    for (uint32_t u = threadIdx.x; u < fd.range_units; u += kBlock) {
-        const EBC_G uint32_t* rp = fd.rpart + 3ull * u;
-        kmin = min(kmin, rp[0]);
-        kmax = max(kmax, rp[1]);
-        bad |= rp[2];
+        for (uint32_t u = threadIdx.x; u < fd.range_units; u += kBlock) {
+            const EBC_G uint64_t* rp = (const EBC_G uint64_t*)fd.rpart + 3ull * u;
+            kmin = min(kmin, rp[0]);
+            kmax = max(kmax, rp[1]);
+            bad |= (uint32_t)rp[2];
+        }
+    } else {
+#pragma unroll 8
+        for (uint32_t u = threadIdx.x; u < fd.range_units; u += kBlock) {
+            const EBC_G uint32_t* rp = fd.rpart + 3ull * u;
+            kmin = min(kmin, (uint64_t)rp[0]);
+            kmax = max(kmax, (uint64_t)rp[1]);
+            bad |= rp[2];
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
-        kmin = min(kmin, (uint32_t)__shfl_xor((int)kmin, o));
-        kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, o));
+        kmin = min(kmin, (uint64_t)__shfl_xor((long long)kmin, o));
+        kmax = max(kmax, (uint64_t)__shfl_xor((long long)kmax, o));
         bad |= (uint32_t)__shfl_xor((int)bad, o);
     }
-    __shared__ uint32_t s_red[3][kWavesPerBlock];
+    __shared__ uint64_t s_red[3][kWavesPerBlock];
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) s_red[0][w] = kmin, s_red[1][w] = kmax, s_red[2][w] = bad;
     __syncthreads();
@@ -126,7 +194,7 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
     for (int k = 1; k < kWavesPerBlock; ++k) {
         kmin = min(kmin, s_red[0][k]);
         kmax = max(kmax, s_red[1][k]);
-        bad |= s_red[2][k];
+        bad |= (uint32_t)s_red[2][k];
     }
     FieldDyn d = {};
     d.status = ST_OK;
@@ -136,10 +204,11 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
         *dy = d;
         return;
     }
-    const float mn = key_float(kmin), mx = key_float(kmax);
+    const double mn = f64 ? key_double(kmin) : (double)key_float((uint32_t)kmin);
+    const double mx = f64 ? key_double(kmax) : (double)key_float((uint32_t)kmax);
     d.mn = mn, d.mx = mx;
-    const double range = (double)mx - (double)mn;
-    const double M = fmax(fabs((double)mn), fabs((double)mx));
+    const double range = mx - mn;  // exact for fp32 ends, rounded once for fp64 ends
+    const double M = fmax(fabs(mn), fabs(mx));
     if (fd.eb_mode == MODE_REL && range == 0.0) {
         d.codec = ARC_CONST;
         *dy = d;
@@ -152,9 +221,23 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
     } else if (eb_abs > 0x1p1000) {
         d.status = ST_ERR_EB;
     } else {
-        int e = -22;
-        if (M != 0.0) e = max(ilogb_pos(M) - ilogb_pos(eb_abs) - 21, -22);
-        if (e > -4) {
+        // fp32 output: eps = 2^max(k - 21, -22), rejected above 2^-4;
+        // fp64 output: eps = 2^max(k - 48, -49), k > 27 rejected (the codes
+        // would leave the int32 range of the Lorenzo arithmetic);
+        // k = ilogb(M) - ilogb(eb_abs)
+        int e = f64 ? -49 : -22;
+        bool too_small = false;
+        if (M != 0.0) {
+            const int k = ilogb_pos(M) - ilogb_pos(eb_abs);
+            if (f64) {
+                too_small = k > 27;
+                e = max(k - 48, -49);
+            } else {
+                e = max(k - 21, -22);
+                too_small = e > -4;
+            }
+        }
+        if (too_small) {
             d.status = ST_ERR_EB_TOO_SMALL;
         } else {
             const double eps = __longlong_as_double((long long)((uint64_t)(1023 + e) << 52));
@@ -167,6 +250,30 @@ __global__ __launch_bounds__(kBlock) void k_params(const FieldDesc* __restrict__
 }
 
 // ------------------------------------------------------ Lorenzo construct
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef f64x2 f64x2_a8 __attribute__((aligned(8)));
+
+// fp64 quads: two 16-byte loads (VEC: 16-byte aligned rows)
+template <bool VEC>
+__device__ __forceinline__ void load_quad(const EBC_G double* __restrict__ p, uint64_t i, int nvalid,
+                                          double v[4])
+{
+    if (nvalid == 4) {
+        f64x2 a, b;
+        if (VEC) {
+            a = __builtin_nontemporal_load((const EBC_G f64x2*)(p + i));
+            b = __builtin_nontemporal_load((const EBC_G f64x2*)(p + i + 2));
+        } else {
+            a = *(const EBC_G f64x2_a8*)(p + i);
+            b = *(const EBC_G f64x2_a8*)(p + i + 2);
+        }
+        v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = k < nvalid ? p[i + k] : 0.0;
+    }
+}
+
 template <bool VEC>
 __device__ __forceinline__ void load_quad(const EBC_G float* __restrict__ p, uint64_t i, int nvalid,
                                           float v[4])
@@ -216,11 +323,16 @@ struct QuantCtx {
 };
 
 // prequant one quad: d = rint(x * inv) in fp64 (Sec. IV-A.1)
-__device__ __forceinline__ void prequant4(const float v[4], double inv, int32_t d[4])
+template <class T>
+__device__ __forceinline__ void prequant4(const T v[4], double inv, int32_t d[4])
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) d[k] = (int32_t)__builtin_rint((double)v[k] * inv);
 }
+
+template <class T> __device__ __forceinline__ const EBC_G T* field_in(const FieldDesc& fd);
+template <> __device__ __forceinline__ const EBC_G float* field_in<float>(const FieldDesc& fd) { return fd.in; }
+template <> __device__ __forceinline__ const EBC_G double* field_in<double>(const FieldDesc& fd) { return fd.in64; }
 
 // postquant one quad of deltas: code, outlier scratch, histogram.
 // Returns a 4-bit mask of outliers among the valid elements.
@@ -259,14 +371,14 @@ __device__ __forceinline__ uint32_t row_count(uint32_t om, uint64_t rowmask)
 
 // One workgroup tile: quantise, record outliers, count codes into the LDS
 // histogram and outlier counts per row segment into `s_cnt` (2D/3D).
-template <int RANK, bool VEC>
+template <int RANK, bool VEC, class T>
 __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl, QuantCtx& qc,
                                                uint32_t* sh_hist, uint32_t* s_cnt,
                                                uint32_t* __restrict__ segs)
 {
     const int l = lane_id();
     const int w = threadIdx.x / kWave;
-    const EBC_G float* __restrict__ in = fd.in;
+    const EBC_G T* __restrict__ in = field_in<T>(fd);
     EBC_G uint16_t* __restrict__ qo = fd.q;
     EBC_G int32_t* __restrict__ dsc = fd.dsc;
     if (RANK == 1) {
@@ -274,7 +386,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
         const uint32_t wt = tl * kWavesPerBlock + w;
         if (wt < fd.n_wave_tiles) {
             const uint64_t n = fd.n;
-            float v[4][4];
+            T v[4][4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint64_t i0 = (uint64_t)wt * 1024 + c * 256 + 4 * l;
@@ -319,7 +431,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
             // planes in flight kAhead ahead of the one being processed (the
             // loop is unrolled, so only those planes occupy registers)
             constexpr int kAhead = 1;
-            float v[8][4];
+            T v[8][4];
 #pragma unroll
             for (int iz = 0; iz < kAhead; ++iz) {
                 const bool ok = yy < ny && z0 + iz < nz;
@@ -364,7 +476,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
             const bool yok = yy < ny;
             uint32_t rowcnt = 0;
             // the four chunks of the wave in flight at once
-            float v[4][4];
+            T v[4][4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const uint32_t x0 = xb * fd.xs + wxi * 64 + 16 * c + 4 * xq;
@@ -415,7 +527,7 @@ __device__ __forceinline__ void flush_hist(const FieldDesc& fd, QuantCtx& qc, ui
 // Persistent over the workgroup tiles of one (rank, layout) group: the grid
 // strides over the tiles, so each workgroup visits every field in one run of
 // consecutive tiles and flushes one partial histogram per field it visits.
-template <int RANK, bool VEC>
+template <int RANK, bool VEC, class T>
 __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restrict__ F, int nf,
                                                       uint32_t n_tiles, uint32_t* __restrict__ seg_cnt)
 {
@@ -442,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
         }
         const uint32_t tl = t - fd.wg_base;
         uint32_t* cnt = s_cnt[par];
-        construct_tile<RANK, VEC>(fd, tl, qc, sh_hist, cnt, seg_cnt + fd.seg_base);
+        construct_tile<RANK, VEC, T>(fd, tl, qc, sh_hist, cnt, seg_cnt + fd.seg_base);
         if (RANK >= 2) {
             __syncthreads();
             // one outlier count per row segment of this tile; the buffer is
@@ -486,10 +598,11 @@ __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restr
 }
 
 // ------------------------------------------------------------- launchers
-hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, hipStream_t s)
+hipError_t launch_range(const FieldDesc* F, int nf, uint32_t units, bool f64, hipStream_t s)
 {
     if (units == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_range, dim3(units), dim3(kBlock), 0, s, F, nf);
+    if (f64) hipLaunchKernelGGL(k_range64, dim3(units), dim3(kBlock), 0, s, F, nf);
+    else hipLaunchKernelGGL(k_range, dim3(units), dim3(kBlock), 0, s, F, nf);
     return hipGetLastError();
 }
 
@@ -499,44 +612,56 @@ hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s)
     return hipGetLastError();
 }
 
+template <class T>
+static hipError_t occupancy(int rank, bool vec, size_t sh, int* per)
+{
+    if (rank == 1)
+        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, true, T>, kBlock, sh)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, false, T>, kBlock, sh);
+    if (rank == 2)
+        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, true, T>, kBlock, sh)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, false, T>, kBlock, sh);
+    return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, true, T>, kBlock, sh)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, false, T>, kBlock, sh);
+}
+
 // Workgroups of one construction variant that the device holds at once (the
 // default persistent grid); 0 if the query fails.
-uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins)
+uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins, bool f64)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     const size_t sh = (size_t)n_bins * sizeof(uint32_t);
-    hipError_t e;
-    if (rank == 1)
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<1, true>, kBlock, sh)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<1, false>, kBlock, sh);
-    else if (rank == 2)
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<2, true>, kBlock, sh)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<2, false>, kBlock, sh);
-    else
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<3, true>, kBlock, sh)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_construct<3, false>, kBlock, sh);
+    const hipError_t e = f64 ? occupancy<double>(rank, vec, sh, &per) : occupancy<float>(rank, vec, sh, &per);
     if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
     return (uint32_t)(per * cus);
 }
 
-hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+template <class T>
+static void construct_launch(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+                             dim3 g, size_t sh, uint32_t* seg_cnt, hipStream_t s)
+{
+    const dim3 b(kBlock);
+    if (rank == 1) {
+        if (vec) hipLaunchKernelGGL((k_construct<1, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<1, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+    } else if (rank == 2) {
+        if (vec) hipLaunchKernelGGL((k_construct<2, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<2, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+    } else {
+        if (vec) hipLaunchKernelGGL((k_construct<3, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<3, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+    }
+}
+
+hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, bool f64, uint32_t wg_tiles,
                             uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s)
 {
     if (wg_tiles == 0) return hipSuccess;
     const size_t sh = (size_t)n_bins * sizeof(uint32_t);
-    const dim3 g(blocks), b(kBlock);
-    if (rank == 1) {
-        if (vec) hipLaunchKernelGGL((k_construct<1, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<1, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-    } else if (rank == 2) {
-        if (vec) hipLaunchKernelGGL((k_construct<2, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<2, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-    } else {
-        if (vec) hipLaunchKernelGGL((k_construct<3, true>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<3, false>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-    }
+    if (f64) construct_launch<double>(F, nf, rank, vec, wg_tiles, dim3(blocks), sh, seg_cnt, s);
+    else construct_launch<float>(F, nf, rank, vec, wg_tiles, dim3(blocks), sh, seg_cnt, s);
     return hipGetLastError();
 }
 

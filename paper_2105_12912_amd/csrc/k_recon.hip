@@ -82,6 +82,41 @@ __device__ __forceinline__ void dequant4(const uint32_t s[4], double ebx2, float
     for (int k = 0; k < 4; ++k) v[k] = (float)((double)(int32_t)s[k] * ebx2);
 }
 
+// fp64 archives: the product rounded once, in binary64
+__device__ __forceinline__ void dequant4(const uint32_t s[4], double ebx2, double v[4])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = (double)(int32_t)s[k] * ebx2;
+}
+
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef f64x2 f64x2_a8 __attribute__((aligned(8)));
+
+// an fp64 quad: two 16-byte stores (non-temporal on 16-byte aligned rows)
+template <bool VEC>
+__device__ __forceinline__ void store_quad(EBC_G double* __restrict__ o, uint64_t i, int nvalid,
+                                           const double v[4])
+{
+    if (nvalid == 4) {
+        if (VEC) {
+            __builtin_nontemporal_store(f64x2{v[0], v[1]}, (EBC_G f64x2*)(o + i));
+            __builtin_nontemporal_store(f64x2{v[2], v[3]}, (EBC_G f64x2*)(o + i + 2));
+        } else {
+            *(EBC_G f64x2_a8*)(o + i) = f64x2{v[0], v[1]};
+            *(EBC_G f64x2_a8*)(o + i + 2) = f64x2{v[2], v[3]};
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (k < nvalid) o[i + k] = v[k];
+    }
+}
+
+// output element type of a field: fp32, or fp64 for fp64 archives
+template <class OT> __device__ __forceinline__ EBC_G OT* field_out(const FieldDesc& fd);
+template <> __device__ __forceinline__ EBC_G float* field_out<float>(const FieldDesc& fd) { return fd.outf; }
+template <> __device__ __forceinline__ EBC_G double* field_out<double>(const FieldDesc& fd) { return fd.outd; }
+
 // This lane's quads of one workgroup tile: four 256-long chunks' quads (1D),
 // four chunks along x (2D) or the eight z-planes of the chunk column (3D).
 template <int RANK>
@@ -143,14 +178,14 @@ __device__ __forceinline__ void rtile_load(const FieldDesc& fd, uint32_t tl, RTi
     }
 }
 
-template <int RANK, bool VEC>
+template <int RANK, bool VEC, class OT>
 __device__ __forceinline__ void rtile_process(const FieldDesc& fd, uint32_t tl, const RTile<RANK>& T,
                                               double ebx2, uint32_t& zeros)
 {
     const int l = lane_id();
     const int32_t r = (int32_t)(fd.n_bins / 2);
     const EBC_G int32_t* __restrict__ dsc = fd.dsc;
-    EBC_G float* __restrict__ out = fd.outf;
+    EBC_G OT* __restrict__ out = field_out<OT>(fd);
     uint32_t zprev[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < RTile<RANK>::NQ; ++k) {
@@ -209,9 +244,9 @@ __device__ __forceinline__ void rtile_process(const FieldDesc& fd, uint32_t tl, 
                 s[j] += dpp_shr_u<8>(s[j]);
             }
         }
-        float v[4];
+        OT v[4];
         dequant4(s, ebx2, v);
-        if (VEC) {
+        if constexpr (VEC && sizeof(OT) == 4) {
             // one unconditional vector store (absent quads go to the sink);
             // a partial quad (1D tail only) is then written element-wise
             st_nt_f4(nv == 4 ? out + i0 : fd.sink, f32x4{v[0], v[1], v[2], v[3]});
@@ -219,7 +254,7 @@ __device__ __forceinline__ void rtile_process(const FieldDesc& fd, uint32_t tl, 
                 for (int j = 0; j < nv; ++j) out[i0 + j] = v[j];
             }
         } else {
-            store_quad<false>(out, i0, nv, v);
+            store_quad<VEC>(out, i0, nv, v);
         }
     }
 }
@@ -243,7 +278,7 @@ __device__ __forceinline__ void flush_zeros(const FieldDesc& fd, uint32_t& zeros
 // next tile's codes in flight while the current tile is reconstructed (two
 // static buffers).  Launched with one workgroup per tile, which measured
 // faster than a resident-size grid; the stride loop serves tuned grids.
-template <int RANK, bool VEC>
+template <int RANK, bool VEC, class OT>
 __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restrict__ F, int nf,
                                                         uint32_t n_tiles)
 {
@@ -268,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
                 cur = fa;
             }
             if (dy->status == ST_OK && dy->codec != ARC_CONST)
-                rtile_process<RANK, VEC>(fd, t - fd.wg_base, A, dy->ebx2, zeros);
+                rtile_process<RANK, VEC, OT>(fd, t - fd.wg_base, A, dy->ebx2, zeros);
         }
         t = tn;
         if (t >= n_tiles) break;
@@ -284,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct(const FieldDesc* __restr
                 cur = fb;
             }
             if (dy->status == ST_OK && dy->codec != ARC_CONST)
-                rtile_process<RANK, VEC>(fd, t - fd.wg_base, B, dy->ebx2, zeros);
+                rtile_process<RANK, VEC, OT>(fd, t - fd.wg_base, B, dy->ebx2, zeros);
         }
         t = tn;
         if (t >= n_tiles) break;
@@ -308,7 +343,7 @@ __device__ __forceinline__ uint32_t zero_half(uint32_t w)
 // 1 and absent elements are not stored.  Outlier codes (0) enter as 0 - r
 // and are only counted here: k_recon3_fix rewrites every chunk that holds
 // one.
-template <bool FULL, bool VEC>
+template <bool FULL, bool VEC, class OT>
 __device__ __forceinline__ void recon3_wave(const FieldDesc& fd, uint32_t x0w, uint32_t y0, uint32_t z0,
                                             double ebx2, uint32_t& zeros)
 {
@@ -318,7 +353,7 @@ __device__ __forceinline__ void recon3_wave(const FieldDesc& fd, uint32_t x0w, u
     const int nvx = x0 < nx ? (int)min<uint32_t>(4, nx - x0) : 0;
     const uint32_t r = fd.n_bins / 2;
     const EBC_G uint16_t* __restrict__ q = fd.q;
-    EBC_G float* __restrict__ out = fd.outf;
+    EBC_G OT* __restrict__ out = field_out<OT>(fd);
     // wave-uniform first element of row y of plane iz (x = x0w)
     auto row = [&](int iz, int y) -> uint64_t { return ((uint64_t)(z0 + iz) * ny + y0 + y) * nx + x0w; };
     auto row_ok = [&](int iz, int y) -> bool { return FULL || (y0 + y < ny && z0 + iz < nz); };
@@ -372,12 +407,12 @@ __device__ __forceinline__ void recon3_wave(const FieldDesc& fd, uint32_t x0w, u
                 sv[k] += zprev[y][k];  // z pass
                 zprev[y][k] = sv[k];
             }
-            float v[4];
+            OT v[4];
             dequant4(sv, ebx2, v);
-            if (FULL) {
+            if constexpr (FULL && sizeof(OT) == 4) {
                 st_nt_f4(out + row(iz, y) + 4 * l, f32x4{v[0], v[1], v[2], v[3]});
             } else {
-                store_quad<VEC>(out, row(iz, y) + 4 * l, nvx, v);
+                store_quad<VEC>(out, row(iz, y) + 4 * l, FULL ? 4 : nvx, v);
             }
         }
     }
@@ -396,7 +431,7 @@ __device__ __forceinline__ void recon3_wave(const FieldDesc& fd, uint32_t x0w, u
 // stream would also wait for every load and store issued before it.  Instead
 // each wave clears its block's chunk flags, which the outlier scatter sets
 // afterwards, and k_recon3_fix recomputes the flagged chunks exactly.
-template <bool VEC>
+template <bool VEC, class OT>
 __global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __restrict__ F, int nf)
 {
     __shared__ uint32_t s_z[kWavesPerBlock];
@@ -414,9 +449,9 @@ __global__ __launch_bounds__(kBlock) void k_reconstruct3(const FieldDesc* __rest
     uint32_t zeros = 0;
     if (lane_id() == 0) fd.oflag[(zb * (nyb * kWavesPerBlock) + yb * kWavesPerBlock + w) * nxb + xb] = 0;
     if (VEC && x0w + 256 <= fd.nx && y0 + 8 <= fd.ny && z0 + 8 <= fd.nz)
-        recon3_wave<true, VEC>(fd, x0w, y0, z0, ebx2, zeros);
+        recon3_wave<true, VEC, OT>(fd, x0w, y0, z0, ebx2, zeros);
     else
-        recon3_wave<false, VEC>(fd, x0w, y0, z0, ebx2, zeros);
+        recon3_wave<false, VEC, OT>(fd, x0w, y0, z0, ebx2, zeros);
     const uint32_t zs = wave_sum_u32(zeros);
     if (lane_id() == 0) s_z[w] = zs;
     __syncthreads();
@@ -484,10 +519,15 @@ __global__ __launch_bounds__(kBlock) void k_recon3_fix(const FieldDesc* __restri
         sv[e] += zl >= 4 ? a : 0u;
     }
     const double ebx2 = dy->ebx2;
-    EBC_G float* __restrict__ out = fd.outf;
+    if (fd.dtype == 1) {
 #pragma unroll
-    for (uint32_t e = 0; e < 8; ++e)
-        if (e < nv) out[i0 + e] = (float)((double)(int32_t)sv[e] * ebx2);
+        for (uint32_t e = 0; e < 8; ++e)
+            if (e < nv) fd.outd[i0 + e] = (double)(int32_t)sv[e] * ebx2;
+    } else {
+#pragma unroll
+        for (uint32_t e = 0; e < 8; ++e)
+            if (e < nv) fd.outf[i0 + e] = (float)((double)(int32_t)sv[e] * ebx2);
+    }
 }
 
 // decompression epilogue: the code-0 count must equal the outlier count
@@ -524,45 +564,37 @@ __global__ __launch_bounds__(kBlock) void k_fill_const(const FieldDesc* __restri
     if (fd.codec_hdr != ARC_CONST || fd.dyn->status != ST_OK) return;
     const uint64_t lo = (uint64_t)(u - fd.range_base) * kRangeUnit;
     const uint64_t hi = min(lo + (uint64_t)kRangeUnit, fd.n);
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) fd.outf[i] = fd.cval;
+    if (fd.dtype == 1) {
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) fd.outd[i] = fd.cval;
+    } else {
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) fd.outf[i] = (float)fd.cval;
+    }
 }
 
-// Workgroups of one reconstruction variant the device holds at once.
-uint32_t reconstruct_resident_blocks(int rank, bool vec)
+template <class OT>
+static void reconstruct_launch(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+                               uint32_t blocks, hipStream_t s)
 {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    hipError_t e;
-    if (rank == 1)
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<1, true>, kBlock, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<1, false>, kBlock, 0);
-    else if (rank == 2)
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, true>, kBlock, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct<2, false>, kBlock, 0);
-    else
-        e = vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct3<true>, kBlock, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_reconstruct3<false>, kBlock, 0);
-    if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
-    return (uint32_t)(per * cus);
+    const dim3 g(blocks), b(kBlock);
+    if (rank == 1) {
+        if (vec) hipLaunchKernelGGL((k_reconstruct<1, true, OT>), g, b, 0, s, F, nf, wg_tiles);
+        else hipLaunchKernelGGL((k_reconstruct<1, false, OT>), g, b, 0, s, F, nf, wg_tiles);
+    } else if (rank == 2) {
+        if (vec) hipLaunchKernelGGL((k_reconstruct<2, true, OT>), g, b, 0, s, F, nf, wg_tiles);
+        else hipLaunchKernelGGL((k_reconstruct<2, false, OT>), g, b, 0, s, F, nf, wg_tiles);
+    } else {
+        const dim3 g3(wg_tiles);  // one workgroup per tile
+        if (vec) hipLaunchKernelGGL((k_reconstruct3<true, OT>), g3, b, 0, s, F, nf);
+        else hipLaunchKernelGGL((k_reconstruct3<false, OT>), g3, b, 0, s, F, nf);
+    }
 }
 
-hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
+hipError_t launch_reconstruct(const FieldDesc* F, int nf, int rank, bool vec, bool f64, uint32_t wg_tiles,
                               uint32_t blocks, hipStream_t s)
 {
     if (wg_tiles == 0) return hipSuccess;
-    const dim3 g(blocks), b(kBlock);
-    if (rank == 1) {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<1, true>), g, b, 0, s, F, nf, wg_tiles);
-        else hipLaunchKernelGGL((k_reconstruct<1, false>), g, b, 0, s, F, nf, wg_tiles);
-    } else if (rank == 2) {
-        if (vec) hipLaunchKernelGGL((k_reconstruct<2, true>), g, b, 0, s, F, nf, wg_tiles);
-        else hipLaunchKernelGGL((k_reconstruct<2, false>), g, b, 0, s, F, nf, wg_tiles);
-    } else {
-        const dim3 g3(wg_tiles);  // one workgroup per tile
-        if (vec) hipLaunchKernelGGL((k_reconstruct3<true>), g3, b, 0, s, F, nf);
-        else hipLaunchKernelGGL((k_reconstruct3<false>), g3, b, 0, s, F, nf);
-    }
+    if (f64) reconstruct_launch<double>(F, nf, rank, vec, wg_tiles, blocks, s);
+    else reconstruct_launch<float>(F, nf, rank, vec, wg_tiles, blocks, s);
     return hipGetLastError();
 }
 

@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restric
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
         const auto* dy = kconst(fd.dyn);
-        if (dy->status != ST_OK || dy->codec != ARC_RLE) {
+        if (dy->status != ST_OK || !rle_codec(dy->codec)) {
             t = skip_field(fd, t);
             continue;
         }
@@ -101,14 +101,25 @@ __global__ __launch_bounds__(kBlock) void k_rle_count(const FieldDesc* __restric
     }
 }
 
+// what: kRleValArc writes the run values into the archive (RLE codec),
+// kRleValSym into the run-value stream of the Huffman pass (RLE+VLE codec),
+// kRleStart the run starts (both codecs; they overwrite the outlier delta
+// scratch, so only after the outlier list is written).
+constexpr int kRleValArc = 1, kRleValSym = 2, kRleStart = 4;
+
 __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restrict__ F, int nf,
-                                                      const uint32_t* __restrict__ roff, uint32_t units)
+                                                      const uint32_t* __restrict__ roff, uint32_t units,
+                                                      int what)
 {
     for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
         const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
         const FieldDesc& fd = F[f];
         const auto* dy = kconst(fd.dyn);
-        if (dy->status != ST_OK || dy->codec != ARC_RLE) {
+        const int32_t codec = dy->codec;
+        const bool val_arc = (what & kRleValArc) && codec == ARC_RLE;
+        const bool val_sym = (what & kRleValSym) && codec == ARC_RLE_VLE;
+        const bool starts = (what & kRleStart) && rle_codec(codec);
+        if (dy->status != ST_OK || !(val_arc || val_sym || starts)) {
             t = skip_field(fd, t) - gridDim.x;  // the loop step adds it back
             continue;
         }
@@ -117,16 +128,57 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
         const uint32_t flags = run_flags(fd, lo, c);
         uint32_t tot;
         uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
-        EBC_G uint16_t* val = (EBC_G uint16_t*)(fd.arc + kHdr);
+        EBC_G uint16_t* val = val_arc ? (EBC_G uint16_t*)(fd.arc + kHdr) : fd.vsym;
         const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
 #pragma unroll
         for (int k = 0; k < kRleItems; ++k) {
             if (flags & (1u << k)) {
-                val[pos] = c[k];
-                fd.rstart[pos] = (uint32_t)(i0 + k);
+                if (val_arc || val_sym) val[pos] = c[k];
+                if (starts) fd.rstart[pos] = (uint32_t)(i0 + k);
                 ++pos;
             }
         }
+    }
+}
+
+// RLE+VLE compress: the run count of each field (from the scanned tile
+// counts) and its run-value histogram cleared; one workgroup per field.
+__global__ __launch_bounds__(kBlock) void k_rle_total(const FieldDesc* __restrict__ F,
+                                                      const uint32_t* __restrict__ roff)
+{
+    const FieldDesc& fd = F[blockIdx.x];
+    EBC_G FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec != ARC_RLE_VLE) return;
+    for (uint32_t b = threadIdx.x; b < fd.n_bins; b += kBlock) fd.vhist[b] = 0;
+    if (threadIdx.x == 0) dy->n_runs = roff[fd.rt_base + fd.n_rt] - roff[fd.rt_base];
+}
+
+// RLE+VLE compress: histogram of the run values, kRleTile values per
+// workgroup, privatised in LDS (the codes' histogram of Sec. II-A step 5,
+// taken over the value stream).
+__global__ __launch_bounds__(kBlock) void k_rle_vhist(const FieldDesc* __restrict__ F, int nf,
+                                                      uint32_t units)
+{
+    extern __shared__ uint32_t sh[];
+    for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
+        const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+        const FieldDesc& fd = F[f];
+        const auto* dy = kconst(fd.dyn);
+        const uint64_t R = dy->n_runs;
+        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+        if (dy->status != ST_OK || dy->codec != ARC_RLE_VLE || lo >= R) {
+            t = skip_field(fd, t) - gridDim.x;
+            continue;
+        }
+        const uint32_t nb = fd.n_bins;
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh[b] = 0;
+        __syncthreads();
+        const uint64_t hi = min(lo + (uint64_t)kRleTile, R);
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&sh[fd.vsym[i]], 1u);
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
+            if (sh[b]) atomicAdd(&fd.vhist[b], sh[b]);
+        __syncthreads();
     }
 }
 
@@ -135,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_len(const FieldDesc* __restrict_
 {
     const FieldDesc& fd = F[blockIdx.y];
     const auto* dy = kconst(fd.dyn);
-    if (dy->status != ST_OK || dy->codec != ARC_RLE) return;
+    if (dy->status != ST_OK || !rle_codec(dy->codec)) return;
     const uint64_t R = dy->n_runs;
     EBC_G uint32_t* len = (EBC_G uint32_t*)(fd.arc + dy->off_rlen);
     for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < R;
@@ -156,7 +208,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_prep(const FieldDesc* __restrict
     const int f = find_field<&FieldDesc::rl_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
-    if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
+    if (!rle_codec(fd.codec_hdr) || k >= fd.n_runs_hdr) return;
     const uint32_t L = ((const EBC_G uint32_t*)(fd.arc + fd.off_rlen))[k];
     if (L == 0 || (uint64_t)L > fd.n) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
     starts[fd.rle_base + k] = L;
@@ -173,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_check(const FieldDesc* __restric
     const int f = find_field<&FieldDesc::rl_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     const uint32_t k = (t - fd.rl_base) * kBlock + threadIdx.x;
-    if (fd.codec_hdr != ARC_RLE || k >= fd.n_runs_hdr) return;
+    if (!rle_codec(fd.codec_hdr) || k >= fd.n_runs_hdr) return;
     const uint32_t* S = starts + fd.rle_base;
     const uint32_t s0 = S[0];
     const uint32_t a = S[k] - s0, b = S[k + 1] - s0;
@@ -192,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
     EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || fd.codec_hdr != ARC_RLE) return;
+    if (dy->status != ST_OK || !rle_codec(fd.codec_hdr)) return;
     const uint32_t* S = starts + fd.rle_base;
     const uint32_t s0 = S[0];
     const uint32_t R = fd.n_runs_hdr;
@@ -217,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     }
     __syncthreads();
     const uint32_t rlo = s_rlo, nr = s_nr;  // nr <= kRleTile because every run is non-empty
-    const EBC_G uint16_t* val = (const EBC_G uint16_t*)(fd.arc + fd.off_val);
+    const EBC_G uint16_t* val = fd.rval;
     for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
         s_start[i] = S[rlo + i] - s0;
         s_val[i] = val[rlo + i];
@@ -262,12 +314,25 @@ hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t
     return hipGetLastError();
 }
 
-hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff,
+hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff, int what,
                             hipStream_t s)
 {
     if (!units) return hipSuccess;
     const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
-    hipLaunchKernelGGL(k_rle_write, dim3(g), dim3(kBlock), 0, s, F, nf, roff, units);
+    hipLaunchKernelGGL(k_rle_write, dim3(g), dim3(kBlock), 0, s, F, nf, roff, units, what);
+    return hipGetLastError();
+}
+
+hipError_t launch_rle_vle_prep(const FieldDesc* F, int nf, uint32_t units, const uint32_t* roff,
+                               uint32_t n_bins, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rle_total, dim3(nf), dim3(kBlock), 0, s, F, roff);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !units) return e;
+    e = launch_rle_write(F, nf, units, roff, kRleValSym, s);
+    if (e != hipSuccess) return e;
+    const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
+    hipLaunchKernelGGL(k_rle_vhist, dim3(g), dim3(kBlock), (size_t)n_bins * 4, s, F, nf, units);
     return hipGetLastError();
 }
 
@@ -279,11 +344,12 @@ hipError_t launch_rle_len(const FieldDesc* F, int nf, uint32_t max_units, hipStr
 }
 
 hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint32_t rt_units,
-                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, hipStream_t s)
+                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, uint32_t scan_direct,
+                             hipStream_t s)
 {
     if (!rl_units) return hipSuccess;
     hipLaunchKernelGGL(k_rle_prep, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
-    hipError_t e = launch_scan(starts, n_starts, tmp, s);
+    hipError_t e = launch_scan(starts, n_starts, tmp, s, scan_direct);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rle_check, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
     if (rt_units) hipLaunchKernelGGL(k_rle_expand, dim3(rt_units), dim3(kBlock), 0, s, F, nf, starts);

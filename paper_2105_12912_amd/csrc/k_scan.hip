@@ -18,7 +18,7 @@ namespace ebc {
 
 constexpr int kScanItems = 16;
 constexpr uint32_t kScanTile = kBlock * kScanItems;
-constexpr uint32_t kScanDirect = 1024;  // tiles up to which the tile sums are not scanned first
+constexpr uint32_t kScanDirect = 1024;  // default: tiles up to which the tile sums are not scanned first
 
 // exclusive scan of one value per thread over the block; *total = block sum
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* total)
@@ -157,15 +157,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_down(uint32_t* __restrict__ a, 
 
 uint32_t scan_tmp_words(uint32_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s)
+hipError_t launch_scan(uint32_t* a, uint32_t n, uint32_t* tmp, hipStream_t s, uint32_t direct_max)
 {
+    if (direct_max == 0) direct_max = kScanDirect;
     if (n == 0) {
         hipLaunchKernelGGL(k_scan_empty, dim3(1), dim3(1), 0, s, a);
         return hipGetLastError();
     }
     const uint32_t nb = (n + kScanTile - 1) / kScanTile;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, a, n, tmp);
-    if (nb <= kScanDirect) {
+    if (nb <= direct_max) {
         hipLaunchKernelGGL(k_scan_down<false>, dim3(nb), dim3(kBlock), 0, s, a, n, tmp, nb);
     } else {
         hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);

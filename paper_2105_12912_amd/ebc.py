@@ -28,16 +28,22 @@ EBC_ERR_ARG, EBC_ERR_DIMS, EBC_ERR_EB, EBC_ERR_EB_TOO_SMALL = -1, -2, -3, -4
 EBC_ERR_BINS, EBC_ERR_NONFINITE, EBC_ERR_OUT_TOO_SMALL, EBC_ERR_WS_TOO_SMALL = -5, -6, -7, -8
 EBC_ERR_ARCHIVE, EBC_ERR_HIP, EBC_ERR_UNSUPPORTED = -9, -10, -11
 EBC_EB_ABS, EBC_EB_REL = 0, 1
-EBC_CODEC_AUTO, EBC_CODEC_HUFFMAN, EBC_CODEC_RLE = 0, 1, 2
-EBC_ARC_HUFFMAN, EBC_ARC_RLE, EBC_ARC_CONST = 0, 1, 2
+EBC_CODEC_AUTO, EBC_CODEC_HUFFMAN, EBC_CODEC_RLE, EBC_CODEC_RLE_VLE, EBC_CODEC_AUTO_VLE = 0, 1, 2, 3, 4
+EBC_ARC_HUFFMAN, EBC_ARC_RLE, EBC_ARC_CONST, EBC_ARC_RLE_VLE = 0, 1, 2, 3
+CODECS = {"auto": EBC_CODEC_AUTO, "huffman": EBC_CODEC_HUFFMAN, "rle": EBC_CODEC_RLE,
+          "rle_vle": EBC_CODEC_RLE_VLE, "auto_vle": EBC_CODEC_AUTO_VLE}
 EBC_STATS_TIMING = 1
 EBC_MAX_STAGES = 16
 HDR_BYTES = 128
 
 
+EBC_F32, EBC_F64 = 0, 1
+
+
 class ebc_params(C.Structure):
     _fields_ = [("eb_mode", C.c_int32), ("codec", C.c_int32), ("eb", C.c_double),
-                ("n_bins", C.c_uint32), ("huff_chunk", C.c_uint32)]
+                ("n_bins", C.c_uint32), ("huff_chunk", C.c_uint32), ("dtype", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ebc_stats(C.Structure):
@@ -46,10 +52,24 @@ class ebc_stats(C.Structure):
                 ("huff_bits", C.c_uint64), ("out_bytes", C.c_uint64), ("eb_abs", C.c_double),
                 ("ebx2", C.c_double), ("value_min", C.c_float), ("value_max", C.c_float),
                 ("n_stages", C.c_uint32), ("stage_ms", C.c_float * EBC_MAX_STAGES),
-                ("stage_name", C.c_char_p * EBC_MAX_STAGES), ("time_only", C.c_char_p)]
+                ("stage_name", C.c_char_p * EBC_MAX_STAGES), ("time_only", C.c_char_p),
+                ("entropy", C.c_double), ("p1", C.c_double), ("r_lo", C.c_double),
+                ("r_hi", C.c_double), ("predict", C.c_int32), ("pad", C.c_int32)]
 
     def stages(self) -> dict:
         return {self.stage_name[k].decode(): float(self.stage_ms[k]) for k in range(self.n_stages)}
+
+
+EBC_MADO_DMAX = 200
+
+
+class ebc_estimates(C.Structure):
+    _fields_ = [("codec_hint", C.c_int32), ("pad", C.c_int32), ("entropy", C.c_double),
+                ("p1", C.c_double), ("r_lo", C.c_double), ("r_hi", C.c_double),
+                ("bits_lo", C.c_double), ("bits_hi", C.c_double), ("hist_max", C.c_uint64),
+                ("n_elems", C.c_uint64), ("samples", C.c_uint64), ("roughness", C.c_double),
+                ("mado_sum", C.c_uint64 * (EBC_MADO_DMAX + 1)),
+                ("mado_cnt", C.c_uint64 * (EBC_MADO_DMAX + 1))]
 
 
 class ebc_field(C.Structure):
@@ -68,7 +88,7 @@ class ebc_archive_ref(C.Structure):
 
 class ebc_tuning_entry(C.Structure):
     _fields_ = [("rank", C.c_int32), ("nx_class", C.c_uint32), ("n_class", C.c_uint32),
-                ("tile_wx", C.c_uint32), ("grid", C.c_uint32)]
+                ("tile_wx", C.c_uint32), ("grid", C.c_uint32), ("scan_direct", C.c_uint32)]
 
 
 class EbcError(RuntimeError):
@@ -104,6 +124,7 @@ _SIGS = {
     "ebc_shape_class": (_I32, [_I32, _P, _P, _P]),
     "ebc_batch_decompress_async": (_I32, [_I32, _P, _P, _P, _U64, _P]),
     "ebc_debug_construct": (_I32, [_P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P]),
+    "ebc_estimate": (_I32, [_P, _I32, _P, _P, _U64, _U64, _P, _P, _U64, _P]),
     "ebc_debug_reconstruct": (_I32, [_P, _P, _P, _U64, _I32, _P, _U32, _F64, _P, _P, _U64, _P]),
 }
 
@@ -198,7 +219,8 @@ def ebc_archive_info(header: bytes) -> dict:
                                 C.byref(total))
     _check(st, "ebc_archive_info")
     return dict(rank=rank.value, dims=tuple(dims), codec=codec.value, n_bins=p.n_bins,
-                huff_chunk=p.huff_chunk, eb=p.eb, eb_mode=p.eb_mode, total=total.value)
+                huff_chunk=p.huff_chunk, eb=p.eb, eb_mode=p.eb_mode, total=total.value,
+                dtype=p.dtype)
 
 
 def ebc_decompress_workspace_size(header: bytes) -> int:
@@ -265,11 +287,13 @@ def ebc_batch_decompress_async(refs, d_statuses, d_ws, ws_bytes, stream) -> int:
 
 
 def ebc_set_tuning(entries) -> int:
-    """entries: iterable of dicts with rank, nx_class, n_class, tile_wx, grid."""
+    """entries: iterable of dicts with rank, nx_class, n_class, tile_wx, grid
+    and optionally scan_direct."""
     entries = list(entries)
     arr = (ebc_tuning_entry * max(len(entries), 1))(
-        *[ebc_tuning_entry(**{k: int(e[k]) for k in ("rank", "nx_class", "n_class", "tile_wx",
-                                                       "grid")}) for e in entries])
+        *[ebc_tuning_entry(**{k: int(e.get(k, 0)) for k in ("rank", "nx_class", "n_class",
+                                                             "tile_wx", "grid", "scan_direct")})
+          for e in entries])
     return lib().ebc_set_tuning(arr if entries else None, len(entries))
 
 
@@ -278,6 +302,14 @@ def ebc_shape_class(rank, dims):
     a, b = C.c_uint32(), C.c_uint32()
     _check(lib().ebc_shape_class(rank, _dims3(dims), C.byref(a), C.byref(b)), "ebc_shape_class")
     return a.value, b.value
+
+
+def ebc_estimate(d_field, rank, dims, params, samples, seed, d_ws, ws_bytes, stream):
+    """Returns (status, ebc_estimates)."""
+    out = ebc_estimates()
+    st = lib().ebc_estimate(d_field, rank, _dims3(dims), C.byref(params), int(samples), int(seed),
+                            C.byref(out), d_ws, ws_bytes, stream)
+    return st, out
 
 
 def ebc_debug_construct(d_field, rank, dims, params, d_q, d_hist, d_oidx, d_oval, d_ws, ws_bytes,
@@ -305,11 +337,20 @@ def _check(st: int, call: str):
 # --------------------------------------------------------------- torch conveniences
 
 def make_params(eb: float, mode: str = "rel", n_bins: int = 1024, codec: str = "auto",
-                huff_chunk: int = 1024) -> ebc_params:
+                huff_chunk: int = 1024, dtype: int = EBC_F32) -> ebc_params:
     return ebc_params(eb_mode=EBC_EB_REL if mode == "rel" else EBC_EB_ABS,
-                      codec={"auto": EBC_CODEC_AUTO, "huffman": EBC_CODEC_HUFFMAN,
-                             "rle": EBC_CODEC_RLE}[codec],
-                      eb=float(eb), n_bins=int(n_bins), huff_chunk=int(huff_chunk))
+                      codec=CODECS[codec],
+                      eb=float(eb), n_bins=int(n_bins), huff_chunk=int(huff_chunk),
+                      dtype=int(dtype), reserved=0)
+
+
+def _dtype_code(x) -> int:
+    torch = _torch()
+    if x.dtype == torch.float32:
+        return EBC_F32
+    if x.dtype == torch.float64:
+        return EBC_F64
+    raise ValueError("fields are float32 or float64 tensors")
 
 
 def _torch():
@@ -362,10 +403,10 @@ def compress(x, eb: float, mode: str = "rel", n_bins: int = 1024, codec: str = "
              out=None):
     """Compress a contiguous fp32 CUDA tensor; returns a uint8 CUDA tensor (and stats)."""
     torch = _torch()
-    if x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous():
-        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    if x.dtype not in (torch.float32, torch.float64) or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 or float64 CUDA tensor")
     rank, dims = field_rank_dims(x)
-    p = make_params(eb, mode, n_bins, codec, huff_chunk)
+    p = make_params(eb, mode, n_bins, codec, huff_chunk, _dtype_code(x))
     bound = ebc_compress_bound(rank, dims, p)
     wsz = ebc_compress_workspace_size(rank, dims, p)
     ws = workspace or default_workspace(x.device)
@@ -417,8 +458,11 @@ def decompress(a, out=None, stream=None, stats: bool | str = False, workspace=No
     info = ebc_archive_info(hdr)
     nx, ny, nz = info["dims"]
     shape = {1: (nx,), 2: (ny, nx), 3: (nz, ny, nx)}[info["rank"]]
+    dt = torch.float64 if info["dtype"] == EBC_F64 else torch.float32
     if out is None:
-        out = torch.empty(shape, dtype=torch.float32, device=a.device)
+        out = torch.empty(shape, dtype=dt, device=a.device)
+    elif out.dtype != dt:
+        raise ValueError(f"output must be {dt} for this archive")
     wsz = ebc_decompress_workspace_size(hdr)
     ws = workspace or default_workspace(a.device)
     wptr, wlen = ws.get(wsz)
@@ -440,7 +484,7 @@ def decompress_status(a, workspace=None) -> int:
         wsz = ebc_decompress_workspace_size(hdr)
     except EbcError as e:
         return e.status
-    out = torch.empty(max(cnt, 1), dtype=torch.float32, device=a.device)
+    out = torch.empty(max(cnt, 1), dtype=torch.float64, device=a.device)  # room for either type
     ws = workspace or default_workspace(a.device)
     wptr, wlen = ws.get(wsz)
     return ebc_decompress(a.data_ptr(), n, out.data_ptr(), out.numel(), wptr, wlen,
@@ -451,7 +495,7 @@ def debug_construct(x, eb: float, mode: str = "rel", n_bins: int = 1024, workspa
     """Quant-codes, histogram and ordered outliers from the construct stage."""
     torch = _torch()
     rank, dims = field_rank_dims(x)
-    p = make_params(eb, mode, n_bins)
+    p = make_params(eb, mode, n_bins, dtype=_dtype_code(x))
     n = x.numel()
     q = torch.empty(n, dtype=torch.int16, device=x.device)
     hist = torch.empty(n_bins, dtype=torch.int32, device=x.device)
@@ -465,6 +509,25 @@ def debug_construct(x, eb: float, mode: str = "rel", n_bins: int = 1024, workspa
                                        _stream_handle(None))
     _check(st, "ebc_debug_construct")
     return dict(q=q, hist=hist, oidx=oidx[:no], oval=oval[:no], ebx2=ebx2)
+
+
+def estimate(x, eb: float, mode: str = "rel", n_bins: int = 1024, samples: int = 1 << 20,
+             seed: int = 0, workspace=None) -> dict:
+    """Compressibility estimates of a field (histogram bounds and madogram)."""
+    rank, dims = field_rank_dims(x)
+    p = make_params(eb, mode, n_bins, dtype=_dtype_code(x))
+    wsz = ebc_compress_workspace_size(rank, dims, p)
+    ws = workspace or default_workspace(x.device)
+    wptr, wlen = ws.get(wsz)
+    st, e = ebc_estimate(x.data_ptr(), rank, dims, p, samples, seed, wptr, wlen,
+                         _stream_handle(None))
+    _check(st, "ebc_estimate")
+    out = {k: getattr(e, k) for k, _ in ebc_estimates._fields_ if k not in ("pad", "mado_sum",
+                                                                            "mado_cnt")}
+    import numpy as np
+    out["mado_sum"] = np.array(e.mado_sum[:], dtype=np.uint64)
+    out["mado_cnt"] = np.array(e.mado_cnt[:], dtype=np.uint64)
+    return out
 
 
 def debug_reconstruct(q, oidx, oval, rank: int, dims, n_bins: int, ebx2: float, workspace=None):

@@ -111,6 +111,22 @@ def random_walk_1d(n: int, seed: int = 4) -> np.ndarray:
     return scale_to(w).astype(np.float32)
 
 
+def sparse_background_1d(n: int, seed: int = 15, active: float = 0.004,
+                         block: int = 4096) -> np.ndarray:
+    """1D field that is constant almost everywhere: blocks of `block` values,
+    each a random-walk segment with probability `active` and otherwise the
+    constant level the walk last reached (a mostly empty domain, the
+    background-dominated case where the run-length workflow wins)."""
+    rng = np.random.default_rng(seed)
+    nb = (n + block - 1) // block
+    on = rng.random(nb) < active
+    steps = np.zeros(nb * block, np.float64)
+    k = int(on.sum())
+    steps.reshape(nb, block)[on] = rng.standard_normal((k, block))
+    x = np.cumsum(steps)[:n]
+    return scale_to(x).astype(np.float32)
+
+
 def grf_field(shape, seed: int, kind: str = "grf") -> np.ndarray:
     if kind == "grf":
         return scale_to(grf(shape, -3.0, seed)).astype(np.float32)

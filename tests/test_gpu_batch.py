@@ -137,13 +137,17 @@ def test_batch_field_error_is_isolated(E, fields, oracle_arcs):
         assert B.outs[i][:res[i][0]].cpu().numpy().tobytes() == oracle_arcs[i]
 
 
-@pytest.mark.parametrize("wx,grid", [(1, 64), (2, 1024), (4, 4096), (1, 16384), (4, 64)])
-def test_tuning_never_changes_bytes(E, fields, oracle_arcs, wx, grid):
+@pytest.mark.parametrize("wx,grid,scan", [(1, 64, 1), (2, 1024, 0), (4, 4096, 1 << 20), (1, 16384, 2),
+                                          (4, 64, 64)])
+def test_tuning_never_changes_bytes(E, fields, oracle_arcs, wx, grid, scan):
+    """Extreme tiles, grids and scan schedules (1: every scan of more than one
+    tile scans its tile sums first; 2^20: never) give the same bytes."""
     entries = []
     for x in fields:
         rank = x.ndim
         nxc, nc = E.ebc_shape_class(rank, tuple(reversed(x.shape)))
-        entries.append(dict(rank=rank, nx_class=nxc, n_class=nc, tile_wx=wx, grid=grid))
+        entries.append(dict(rank=rank, nx_class=nxc, n_class=nc, tile_wx=wx, grid=grid,
+                            scan_direct=scan))
     assert E.ebc_set_tuning(entries) == 0
     try:
         ws = E.Workspace("cuda")

@@ -372,3 +372,20 @@ def test_corrupt_rle_archives_rejected(E):
         b[off_len:off_len + 4 * R] = L.astype(np.uint32).view(np.uint8)
         assert O.decompress_status(b.tobytes()) == -9, mutate
         assert E.decompress_status(dev(b)) == E.EBC_ERR_ARCHIVE, mutate
+
+
+@pytest.mark.parametrize("hc", [8192, 65536])
+def test_huffman_chunks_longer_than_a_pass(E, hc):
+    """Chunks longer than one encode pass (4096 symbols): the encoder carries
+    the partial word between passes; the decoder starts every 256-symbol
+    sub-chunk on its own.  Fields span several chunks and end on a short one."""
+    for x in (rng_field((300, 500), 15, "grf"), rng_field((70, 90), 16, "noise")):
+        ref = O.compress(x, 1e-4, codec="huffman", hc=hc)
+        a = E.compress(dev(x), 1e-4, codec="huffman", huff_chunk=hc)
+        assert a.cpu().numpy().tobytes() == ref
+        np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))
+    # codewords longer than 32 bits across passes
+    xf, _ = fibonacci_deltas_field(34, 33)
+    ref = O.compress(xf, 0.5, "abs", codec="huffman", hc=hc)
+    a = E.compress(dev(xf), 0.5, "abs", codec="huffman", huff_chunk=hc)
+    assert a.cpu().numpy().tobytes() == ref

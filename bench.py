@@ -39,6 +39,9 @@ WORKLOADS = {
                lambda s: s.climate_2d(), 1e-4),
     "smooth256": ("GRF 2D 256x256 fp32, rel eb 1e-4, 1024 bins",
                   lambda s: s.smooth_2d(256, 256, 1), 1e-4),
+    "sparse1d": ("1D 1.2e8 fp32, constant except 0.4% random-walk blocks, rel eb 1e-2, 1024 bins "
+                 "(the 1.09-bit rule picks run-length coding)",
+                 lambda s: s.sparse_background_1d(120_000_000), 1e-2),
 }
 
 # kernel stage -> algorithmic bytes per launch (n elements, o outliers, w words, r runs);
@@ -588,7 +591,7 @@ def main():
         "decompress_GBps": round(gb / (dec_ms / 1e3), 3),
         "compress_ms": round(comp_ms, 4), "decompress_ms": round(dec_ms, 4),
         "archive_bytes": len(arc), "compression_ratio": round(x.nbytes / len(arc), 3),
-        "codec": ["huffman", "rle", "const"][info["codec"]],
+        "codec": ["huffman", "rle", "const", "rle_vle"][info["codec"]],
         "max_abs_err": err, "error_bound_ok": ok_bound,
     }
     if timing and last_cs is not None:

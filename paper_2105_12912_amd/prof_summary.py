@@ -41,6 +41,9 @@ KERNEL_SOURCES = {
     "k_huff_write": ["paper_2105_12912_amd/csrc/k_huffman.hip"],
     "k_huff_bits": ["paper_2105_12912_amd/csrc/k_huffman.hip"],
     "k_range": ["paper_2105_12912_amd/csrc/k_quant.hip"],
+    "k_rle_count": ["paper_2105_12912_amd/csrc/k_rle.hip"],
+    "k_rle_write": ["paper_2105_12912_amd/csrc/k_rle.hip"],
+    "k_rle_expand": ["paper_2105_12912_amd/csrc/k_rle.hip"],
 }
 COMMON_SOURCES = ["paper_2105_12912_amd/csrc/ebc_dev.h", "paper_2105_12912_amd/csrc/ebc_types.h"]
 

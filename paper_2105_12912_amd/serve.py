@@ -385,8 +385,16 @@ def run_stream(server: Server, stream, make_input, archive_pool: int = 32, warmu
     # measured window: first measured arrival to last measured completion
     span = max(r.t_done for r in ok) - min(r.t_arrival for r in ok) if ok else 0.0
     nbytes = sum(r.nbytes for r in ok)
+    # requests the library refused, by status (e.g. a short slice of a smooth
+    # field whose relative bound falls below fp32 resolution)
+    errors = {}
+    for r in reqs:
+        if r.status != ebc.EBC_OK:
+            key = f"{r.status} {ebc.status_string(r.status)}"
+            errors[key] = errors.get(key, 0) + 1
     return {
         "requests": len(reqs), "ok": sum(r.status == ebc.EBC_OK for r in reqs),
+        "errors": errors,
         "measured": len(ok),
         "compress": sum(r.op == "compress" for r in ok),
         "decompress": sum(r.op == "decompress" for r in ok),

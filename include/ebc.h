@@ -86,9 +86,9 @@ typedef struct ebc_params {
     int32_t codec;       /* EBC_CODEC_* */
     double eb;           /* error bound (absolute value, or fraction of the range) */
     uint32_t n_bins;     /* quantisation bins (cap = 2 * radius, Algorithm 1); even,
-                            4..65536; this GPU path implements n_bins <= 4096 */
-    uint32_t huff_chunk; /* symbols per Huffman chunk: 0 selects 1024; power of two;
-                            this GPU path implements 64..4096 */
+                            4..65536 (above 4096 the per-bin tables live in HBM) */
+    uint32_t huff_chunk; /* symbols per Huffman chunk: 0 selects 1024; power of two
+                            in 64..65536 */
     int32_t dtype;       /* EBC_F32 or EBC_F64: element type of the field to compress */
     int32_t reserved;    /* 0 */
 } ebc_params;

@@ -122,8 +122,6 @@ int check_params(const ebc_params* p, Params* out)
     const uint32_t hc = p->huff_chunk ? p->huff_chunk : 1024u;
     if (hc < 64 || hc > 65536 || (hc & (hc - 1)))
         return fail(EBC_ERR_ARG, "huff_chunk must be a power of two in [64, 65536]");
-    if (p->n_bins > kMaxBins)
-        return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented on this GPU path", kMaxBins);
     out->eb_mode = p->eb_mode;
     out->codec = p->codec;
     out->eb = p->eb;
@@ -243,9 +241,11 @@ struct Batch {
     uint32_t scan = 0;      // scan schedule of the call (largest tuned value of its fields)
     FieldDesc* d_fd = nullptr;
     FieldDyn* d_dyn = nullptr;
-    uint32_t *d_seg = nullptr, *d_wcnt = nullptr, *d_rcnt = nullptr, *d_starts = nullptr,
+    uint32_t *d_seg = nullptr, *d_wcnt = nullptr, *d_rcnt = nullptr, *d_starts = nullptr, *d_tmap = nullptr,
              *d_tmp = nullptr, *d_soff = nullptr;
     uint8_t* d_tabs = nullptr;
+    size_t tab_stride = 0;  // decompress: decoder table bytes per field (largest n_bins of the batch)
+    uint32_t max_bins = 0;
     uint64_t* d_result = nullptr;
     EstDev* d_est = nullptr;
     uint64_t ws_bytes = 0;
@@ -419,10 +419,11 @@ int plan_compress(Batch& B, const std::vector<CompressIn>& fin, const Params& P,
         d.dsc = bp.take<int32_t>(4 * g.n);
         d.rstart = (uint32_t*)d.dsc;  // used only after the outliers are written
         d.hist = bp.take<uint32_t>(4ull * P.n_bins);
-        d.hpart = bp.take<uint32_t>(4ull * P.n_bins * d.hrows);
+        d.hpart = bp.take<uint32_t>(4ull * hist_slots(P.n_bins) * d.hrows);
         d.rpart = bp.take<uint32_t>(24ull * g.range_units);  // room for 64-bit keys
         d.code = bp.take<uint64_t>(8ull * P.n_bins);
         d.len = bp.take<uint8_t>(P.n_bins);
+        d.cbs = P.n_bins > kMaxBins ? bp.take<uint8_t>(codebook_wide_scratch_bytes(P.n_bins)) : nullptr;
         d.hbits = bp.take<uint32_t>(4ull * g.n_hch);
         // RLE+VLE requested: the run values (at most N, and the encoder may
         // read 30 bytes past the stream) and their histogram
@@ -505,7 +506,7 @@ int enqueue_compress(Batch& B, const Params& P, hipStream_t s, Timer& T, bool de
     HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, 0, s));
     const bool vle = P.codec == EBC_CODEC_RLE_VLE || P.codec == EBC_CODEC_AUTO_VLE;
     T.mark("encode_count");
-    HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, 0, s));
+    HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, P.n_bins, B.d_wcnt, 0, s));
     HIP_TRY(launch_rle_count(B.d_fd, nf, B.tot_rt, B.d_rcnt, s));
     T.mark("encode_scan");
     HIP_TRY(launch_scan(B.d_rcnt, B.tot_rt, B.d_tmp, s, B.scan));
@@ -515,7 +516,7 @@ int enqueue_compress(Batch& B, const Params& P, hipStream_t s, Timer& T, bool de
         T.mark("rle_vle");
         HIP_TRY(launch_rle_vle_prep(B.d_fd, nf, B.tot_rt, B.d_rcnt, P.n_bins, s));
         HIP_TRY(launch_codebook(B.d_fd, nf, P.n_bins, 1, s));
-        HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, B.d_wcnt, 1, s));
+        HIP_TRY(launch_huff_bits(B.d_fd, nf, B.tot_hwg, P.hc, P.n_bins, B.d_wcnt, 1, s));
     }
     HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s, B.scan));
     T.mark("layout");
@@ -658,7 +659,6 @@ int header_supported(const Header& H)
     for (int k = 0; k < 3; ++k)
         if (H.chunk[k] != want[H.rank - 1][k])
             return fail(EBC_ERR_UNSUPPORTED, "non-default Lorenzo chunk not implemented");
-    if (H.n_bins > kMaxBins) return fail(EBC_ERR_UNSUPPORTED, "n_bins > %u not implemented", kMaxBins);
     return EBC_OK;
 }
 
@@ -744,8 +744,12 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
     B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
     B.d_soff = bp.take<uint32_t>(4ull * (B.tot_sub + 1));
     B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
+    B.d_tmap = bp.take<uint32_t>(4ull * (B.tot_rt + 1));
     B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(std::max(B.tot_hch, B.tot_runs)));
-    B.d_tabs = bp.take<uint8_t>(dectab_bytes() * B.nf);
+    B.max_bins = 0;
+    for (int k = 0; k < B.nf; ++k) B.max_bins = std::max(B.max_bins, din[B.order[k]].H.n_bins);
+    B.tab_stride = dectab_bytes(B.max_bins);
+    B.d_tabs = bp.take<uint8_t>(B.tab_stride * B.nf);
     B.d_result = bp.take<uint64_t>(16);
     for (int k = 0; k < B.nf; ++k) {
         const DecompressIn& D = din[B.order[k]];
@@ -830,13 +834,13 @@ int enqueue_decompress(Batch& B, hipStream_t s, Timer& T)
         HIP_TRY(launch_scan(B.d_wcnt, B.tot_hch, B.d_tmp, s, B.scan));
         HIP_TRY(launch_words_check(B.d_fd, nf, B.d_wcnt, s));
         T.mark("dectab");
-        HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, s));
+        HIP_TRY(launch_dectab(B.d_fd, nf, B.d_tabs, B.tab_stride, B.max_bins, s));
         T.mark("huffman_decode");
-        HIP_TRY(launch_huff_decode(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, B.d_soff, B.d_tabs, dectab_bytes(), s));
+        HIP_TRY(launch_huff_decode(B.d_fd, nf, B.tot_hdwg, B.d_wcnt, B.d_soff, B.d_tabs, B.tab_stride, s));
     }
     if (B.tot_runs) {
         T.mark("rle_decode");
-        HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmp, B.tot_runs, B.scan, s));
+        HIP_TRY(launch_rle_decode(B.d_fd, nf, B.tot_rl, B.tot_rt, B.d_starts, B.d_tmap, B.d_tmp, B.tot_runs, B.scan, s));
     }
     const int st = enqueue_reconstruct(B, s, T);
     if (st) return st;
@@ -1442,7 +1446,7 @@ int ebc_debug_reconstruct(const uint16_t* d_q, const uint32_t* d_oidx, const int
     Header H = {};
     int st = check_dims(rank, dims, &H.n);
     if (st) return st;
-    if (n_bins < 4 || n_bins > kMaxBins || (n_bins & 1)) return fail(EBC_ERR_BINS, "bad n_bins");
+    if (n_bins < 4 || n_bins > kBinsLimit || (n_bins & 1)) return fail(EBC_ERR_BINS, "bad n_bins");
     H.rank = rank;
     memcpy(H.dims, dims, sizeof(H.dims));
     H.codec = EBC_ARC_HUFFMAN;

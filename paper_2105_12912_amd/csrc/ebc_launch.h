@@ -37,7 +37,9 @@ hipError_t launch_hist_reduce(const FieldDesc* F, int nf, uint32_t n_bins, hipSt
 // codebook
 size_t codebook_lds_bytes(uint32_t n_bins);
 hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, int pass, hipStream_t s);
-hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, hipStream_t s);
+hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, size_t stride, uint32_t max_bins,
+                         hipStream_t s);
+size_t codebook_wide_scratch_bytes(uint32_t n_bins);
 
 // compressibility estimates (histogram bounds; madogram over `samples` pairs)
 hipError_t launch_estimate(const FieldDesc* F, int nf, EstDev* est, uint64_t samples, uint64_t seed,
@@ -45,8 +47,8 @@ hipError_t launch_estimate(const FieldDesc* F, int nf, EstDev* est, uint64_t sam
 
 // Huffman
 size_t huff_write_lds_bytes(uint32_t n_bins, uint32_t hc);
-hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t* wcnt,
-                            int which, hipStream_t s);
+hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t n_bins,
+                            uint32_t* wcnt, int which, hipStream_t s);
 hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_t hc,
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s);
 hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, hipStream_t s);
@@ -67,8 +69,8 @@ hipError_t launch_rle_vle_prep(const FieldDesc* F, int nf, uint32_t units, const
                                uint32_t n_bins, hipStream_t s);
 hipError_t launch_rle_len(const FieldDesc* F, int nf, uint32_t max_units, hipStream_t s);
 hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint32_t rt_units,
-                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, uint32_t scan_direct,
-                             hipStream_t s);
+                             uint32_t* starts, uint32_t* tmap, uint32_t* tmp, uint32_t n_starts,
+                             uint32_t scan_direct, hipStream_t s);
 
 // outliers
 uint32_t outlier_write_units(uint32_t n_seg);

@@ -25,7 +25,10 @@ constexpr int kWave = 64;
 constexpr int kBlock = 256;                 // threads per workgroup everywhere
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr uint32_t kHdr = 128;              // archive header bytes
-constexpr uint32_t kMaxBins = 4096;         // n_bins this GPU path implements
+constexpr uint32_t kMaxBins = 4096;         // n_bins whose per-bin tables fit in LDS ("narrow")
+constexpr uint32_t kBinsLimit = 65536;      // largest n_bins of the format (wide above kMaxBins)
+constexpr uint32_t kHistWin = 4096;         // wide bins: LDS histogram slots (code 0 + a window
+                                            // of codes around the centre; others counted in HBM)
 constexpr uint32_t kPassHc = 4096;          // Huffman chunk symbols an encode pass covers
 constexpr uint32_t kRangeUnit = 16384;      // elements per value-range work unit
 constexpr uint32_t kRleTile = 4096;         // elements per RLE work unit
@@ -112,6 +115,7 @@ struct FieldDesc {
     EBC_G uint32_t* rpart;   // range partials: 3 words per range unit (3 x 64 bits for fp64)
     EBC_G uint64_t* code;    // n_bins packed codewords: (len << 56) | code
     EBC_G uint8_t* len;      // n_bins code lengths
+    EBC_G uint8_t* cbs;      // wide bins: codebook scratch (codebook_wide_scratch_bytes)
     EBC_G uint32_t* hbits;   // per Huffman chunk bit counts
     EBC_G uint32_t* rstart;  // RLE run starts (compress scratch)
     EBC_G uint16_t* vsym;    // RLE+VLE: run values (compress: source of the Huffman pass;
@@ -180,13 +184,23 @@ struct DecTab {
     uint32_t pad;
     uint64_t lut[1u << kLutBits];
     uint32_t l2[kL2Size];
-    uint16_t perm[kMaxBins];  // symbols ordered by (length, symbol)
+    uint16_t perm[2];         // symbols ordered by (length, symbol): n_bins entries (the
+                              // table occupies dectab_bytes(n_bins))
 };
 
 // chunks per encode workgroup (one per wave); chunks longer than kPassHc
 // symbols are encoded by one wave in passes of kPassHc
 __host__ __device__ constexpr uint32_t huff_cpw(uint32_t hc) { return hc <= 1024 ? 4 : hc <= kPassHc ? kPassHc / hc : 1; }
 
-__host__ __device__ constexpr size_t dectab_bytes() { return (sizeof(DecTab) + 255) & ~(size_t)255; }
+// histogram slots a construction workgroup keeps in LDS for n_bins bins
+__host__ __device__ constexpr uint32_t hist_slots(uint32_t nb) { return nb > kMaxBins ? kHistWin : nb; }
+// wide bins: the first code of the LDS window (slot 1); slot 0 is code 0
+__host__ __device__ constexpr uint32_t hist_win_lo(uint32_t nb) { return nb / 2 - (kHistWin / 2 - 1); }
+
+// decoder table bytes for n_bins symbols (the permutation grows with n_bins)
+__host__ __device__ constexpr size_t dectab_bytes(uint32_t nb)
+{
+    return (offsetof(DecTab, perm) + 2 * (size_t)(nb > 2 ? nb : 2) + 255) & ~(size_t)255;
+}
 
 }  // namespace ebc

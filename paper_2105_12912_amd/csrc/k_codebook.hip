@@ -363,6 +363,283 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
     }
 }
 
+// ------------------------------------------------- wide bins (> kMaxBins)
+// The same construction for n_bins up to 65536, whose per-symbol arrays do
+// not fit in LDS: keys, internal weights, parents and depths live in a
+// per-field scratch of the workspace (codebook_wide_scratch_bytes), one
+// workgroup per field, every phase separated by workgroup barriers.  The
+// internal weights are summed with atomics, so they are read back with
+// atomic loads (the vector L1 is not kept coherent with L2 atomics).
+
+size_t codebook_wide_scratch_bytes(uint32_t n_bins)
+{
+    const size_t P = pow2ceil(n_bins);
+    return 8 * P + 4 * P + 4 * (4 * P) + 4 * (4 * P);  // keys, weights, 2 x 2P parents, 2 x 2P depths
+}
+
+__device__ __forceinline__ uint32_t ld_atomic(const EBC_G uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Running per-length ranks over the symbols in blocks of kCb: for symbol s of
+// length L (0 = unused) returns the number of symbols of length L below s;
+// run[65] (LDS) carries the per-length totals from block to block, wc[16][65]
+// is LDS scratch.  Uniform loop; every thread calls it for its symbol.
+__device__ __forceinline__ uint32_t blocked_rank(uint32_t L, uint32_t* run, uint32_t (*wc)[65])
+{
+    const int l = lane_id();
+    const int w = threadIdx.x / kWave;
+    uint64_t todo = ballot(L != 0);
+    uint32_t rk = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t LL = __shfl(L, leader);
+        const uint64_t m = ballot(L == LL);
+        if (L == LL) rk = __popcll(m & ((1ull << l) - 1));
+        if (l == 0) wc[w][LL] = (uint32_t)__popcll(m);
+        todo &= ~m;
+    }
+    __syncthreads();
+    uint32_t off = 0;
+    if (L) {
+        off = run[L];
+        for (int v = 0; v < w; ++v) off += wc[v][L];
+    }
+    __syncthreads();
+    if (threadIdx.x < 65) {
+        uint32_t t = 0;
+        for (int v = 0; v < kCbWaves; ++v) {
+            t += wc[v][threadIdx.x];
+            wc[v][threadIdx.x] = 0;
+        }
+        run[threadIdx.x] += t;
+    }
+    __syncthreads();
+    return off + rk;
+}
+
+__global__ __launch_bounds__(kCb) void k_codebook_wide(const FieldDesc* __restrict__ F, int pass)
+{
+    const FieldDesc& fd = F[blockIdx.x];
+    EBC_G FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
+    if (pass == 1 && dy->codec != ARC_RLE_VLE) return;
+    const EBC_G uint32_t* __restrict__ hist = pass == 0 ? fd.hist : fd.vhist;
+    const uint32_t nb = fd.n_bins;
+    const uint32_t P0 = pow2ceil(nb);
+    EBC_G uint64_t* keys = (EBC_G uint64_t*)fd.cbs;
+    EBC_G uint32_t* iw = (EBC_G uint32_t*)(keys + P0);
+    // nodes: m leaves then m - 1 internal ones, below 2 P0
+    EBC_G uint32_t* par[2] = {iw + P0, iw + 3 * P0};
+    EBC_G uint32_t* dep[2] = {iw + 5 * P0, iw + 7 * P0};
+    __shared__ uint32_t wc[kCbWaves][65];
+    __shared__ uint32_t run[65];
+    __shared__ uint64_t first[65];
+    __shared__ uint32_t s_li, s_ih, s_ni, s_cl, s_ci;
+    __shared__ uint64_t s_bits[kCbWaves];
+    for (uint32_t i = threadIdx.x; i < kCbWaves * 65; i += kCb) (&wc[0][0])[i] = 0;
+    if (threadIdx.x < 65) run[threadIdx.x] = 0;
+    __syncthreads();
+
+    // used symbols in symbol order, keyed (freq << 16) | symbol
+    for (uint32_t b0 = 0; b0 < nb; b0 += kCb) {
+        const uint32_t s = b0 + threadIdx.x;
+        const uint32_t h = s < nb ? hist[s] : 0u;
+        const uint32_t pos = blocked_rank(h ? 1u : 0u, run, wc);
+        if (h) keys[pos] = ((uint64_t)h << 16) | s;
+    }
+    const uint32_t m = run[1];
+    if (m == 0) {
+        if (threadIdx.x == 0) dy->status = ST_ERR_ARCHIVE;
+        return;
+    }
+    // ascending bitonic sort of the m keys, padded to a power of two
+    const uint32_t P = pow2ceil(m);
+    for (uint32_t i = m + threadIdx.x; i < P; i += kCb) keys[i] = ~0ull;
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            for (uint32_t i = threadIdx.x; i < P; i += kCb) {
+                const uint32_t q = i ^ j;
+                if (q > i) {
+                    const uint64_t a = keys[i], b = keys[q];
+                    const bool up = (i & k) == 0;
+                    if ((a > b) == up) keys[i] = b, keys[q] = a;
+                }
+            }
+        }
+    }
+    // two-queue merge in parallel rounds (as in k_codebook): every available
+    // item not heavier than the next internal node pairs up in merged order
+    if (threadIdx.x == 0) s_li = 0, s_ih = 0, s_ni = 0;
+    auto lw = [&](uint32_t i) { return (uint32_t)(keys[i] >> 16); };
+    for (;;) {
+        __syncthreads();
+        const uint32_t li = s_li, ih = s_ih, ni = s_ni;
+        if (ni + 1 >= m) break;
+        if (threadIdx.x == 0) {
+            const uint32_t l0 = li < m ? lw(li) : 0xFFFFFFFFu, l1 = li + 1 < m ? lw(li + 1) : 0xFFFFFFFFu;
+            const uint32_t i0 = ih < ni ? ld_atomic(iw + ih) : 0xFFFFFFFFu;
+            const uint32_t i1 = ih + 1 < ni ? ld_atomic(iw + ih + 1) : 0xFFFFFFFFu;
+            uint32_t t, a = li, b = ih;
+            {
+                const bool f0 = a < m && (b == ni || l0 <= i0);
+                t = f0 ? l0 : i0;
+                a += f0, b += !f0;
+                const uint32_t la = a == li ? l0 : l1, ib = b == ih ? i0 : i1;
+                const bool f1 = a < m && (b == ni || la <= ib);
+                t += f1 ? la : ib;
+            }
+            // both queues are sorted: binary searches for the items <= t
+            uint32_t lo = li, hi = m;
+            while (lo < hi) {
+                const uint32_t md = (lo + hi) >> 1;
+                if (lw(md) <= t) lo = md + 1;
+                else hi = md;
+            }
+            s_cl = lo - li;
+            lo = ih, hi = ni;
+            while (lo < hi) {
+                const uint32_t md = (lo + hi) >> 1;
+                if (ld_atomic(iw + md) <= t) lo = md + 1;
+                else hi = md;
+            }
+            s_ci = lo - ih;
+        }
+        __syncthreads();
+        const uint32_t cl = s_cl, ci = s_ci, np = (cl + ci) / 2;
+        if (np == 0) {
+            // cannot happen (the two lightest items always pair); guards the loop
+            if (threadIdx.x == 0) dy->status = ST_ERR_ARCHIVE;
+            return;
+        }
+        for (uint32_t k = threadIdx.x; k < np; k += kCb)
+            __hip_atomic_store(iw + ni + k, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cl; i += kCb) {
+            const uint32_t wi = lw(li + i);
+            uint32_t lo = 0, hi = ci;  // internal nodes lighter than the leaf
+            while (lo < hi) {
+                const uint32_t md = (lo + hi) >> 1;
+                if (ld_atomic(iw + ih + md) < wi) lo = md + 1;
+                else hi = md;
+            }
+            const uint32_t pos = i + lo;
+            if (pos < 2 * np) {
+                par[0][li + i] = m + ni + pos / 2;
+                atomicAdd(iw + ni + pos / 2, wi);
+            }
+        }
+        for (uint32_t j = threadIdx.x; j < ci; j += kCb) {
+            const uint32_t wj = ld_atomic(iw + ih + j);
+            uint32_t lo = 0, hi = cl;  // leaves not heavier than the node
+            while (lo < hi) {
+                const uint32_t md = (lo + hi) >> 1;
+                if (lw(li + md) <= wj) lo = md + 1;
+                else hi = md;
+            }
+            const uint32_t pos = j + lo;
+            if (pos < 2 * np) {
+                par[0][m + ih + j] = m + ni + pos / 2;
+                atomicAdd(iw + ni + pos / 2, wj);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t dl = cl, di = ci;
+            if ((cl + ci) & 1) {
+                bool last_is_leaf;
+                if (ci == 0) last_is_leaf = true;
+                else if (cl == 0) last_is_leaf = false;
+                else last_is_leaf = lw(li + cl - 1) > ld_atomic(iw + ih + ci - 1);
+                if (last_is_leaf) --dl;
+                else --di;
+            }
+            s_li = li + dl, s_ih = ih + di, s_ni = ni + np;
+        }
+    }
+    // depths by pointer jumping (ping-pong buffers); a lone symbol gets one bit
+    const uint32_t nn = m > 1 ? 2 * m - 1 : 1;
+    const uint32_t root = nn - 1;
+    for (uint32_t v = threadIdx.x; v < nn; v += kCb) {
+        dep[0][v] = m == 1 ? 1u : (v == root ? 0u : 1u);
+        if (v == root) par[0][v] = v;
+    }
+    int cur = 0;
+    if (m > 1) {
+        for (int round = 0; round < 7; ++round) {
+            __syncthreads();
+            for (uint32_t v = threadIdx.x; v < nn; v += kCb) {
+                const uint32_t a = par[cur][v];
+                dep[cur ^ 1][v] = min(dep[cur][v] + (a == v ? 0u : dep[cur][a]), 255u);
+                par[cur ^ 1][v] = par[cur][a];
+            }
+            cur ^= 1;
+        }
+    }
+    __syncthreads();
+    // leaf lengths -> symbols, per-length counts
+    for (uint32_t s2 = threadIdx.x; s2 < nb; s2 += kCb) fd.len[s2] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < m; i += kCb) fd.len[keys[i] & 0xFFFFu] = (uint8_t)dep[cur][i];
+    if (threadIdx.x < 65) run[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t s2 = threadIdx.x; s2 < nb; s2 += kCb) {
+        const uint32_t L = fd.len[s2];
+        if (L) atomicAdd(&run[L], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t c = 0;
+        uint32_t maxl = 0;
+        for (int L = 1; L <= 64; ++L) {
+            first[L] = c;
+            c = (c + run[L]) << 1;
+            if (run[L]) maxl = L;
+        }
+        dy->max_len = maxl;
+        dy->n_used = m;
+    }
+    __syncthreads();
+    if (threadIdx.x < 65) run[threadIdx.x] = 0;
+    __syncthreads();
+    // canonical codes in (length, symbol) order
+    uint64_t bits = 0;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kCb) {
+        const uint32_t s2 = b0 + threadIdx.x;
+        const uint32_t L = s2 < nb ? fd.len[s2] : 0u;
+        const uint32_t rk = blocked_rank(L, run, wc);
+        if (s2 < nb) {
+            uint64_t packed = 0;
+            if (L) {
+                packed = ((uint64_t)L << 56) | (first[L] + rk);
+                bits += (uint64_t)hist[s2] * L;
+            }
+            fd.code[s2] = packed;
+        }
+    }
+    bits = wave_sum_u64(bits);
+    if (lane_id() == 0) s_bits[threadIdx.x / kWave] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0 && pass == 0) {
+        uint64_t tb = 0;
+        for (int k = 0; k < kCbWaves; ++k) tb += s_bits[k];
+        dy->huff_bits = tb;
+        const bool rle = 100ull * tb <= 109ull * fd.n;
+        int codec;
+        switch (fd.codec_req) {
+        case REQ_AUTO: codec = rle ? ARC_RLE : ARC_HUFFMAN; break;
+        case REQ_AUTO_VLE: codec = rle ? ARC_RLE_VLE : ARC_HUFFMAN; break;
+        case REQ_HUFFMAN: codec = ARC_HUFFMAN; break;
+        case REQ_RLE: codec = ARC_RLE; break;
+        default: codec = ARC_RLE_VLE; break;
+        }
+        dy->codec = codec;
+        dy->n_out = fd.hist[0];
+    }
+}
+
 // ------------------------------------------------------- decoder tables
 // From the code lengths stored in an archive: per-length counts, first codes
 // and offsets, the symbol permutation in (length, symbol) order and a
@@ -370,13 +647,117 @@ __global__ __launch_bounds__(kCb) void k_codebook(const FieldDesc* __restrict__ 
 
 
 
+// The lookup tables of a decoder table T from the per-length counts, first
+// codes and offsets (LDS) and the (length, symbol) permutation, read through
+// perm(i) (LDS for narrow bins, T->perm in HBM for wide ones).  Called by every
+// thread of the workgroup after a barrier.
+template <class PERM>
+__device__ __forceinline__ void dectab_tables(DecTab* T, const uint32_t* cntL, const uint64_t* first,
+                                              const uint32_t* offs, uint32_t maxl_in, PERM perm)
+{
+    // left-aligned ends of the code space of lengths <= L (monotone in L)
+    __syncthreads();
+    if (threadIdx.x <= 64) {
+        const uint32_t L = threadIdx.x;
+        const uint32_t maxl = maxl_in;
+        uint64_t endv = ~0ull;
+        if (L >= 1 && L < maxl) endv = (first[L] + cntL[L]) << (64 - L);
+        T->endv[L] = endv;
+    }
+    // Multi-symbol lookup table in two steps.  t1[p]: the codeword (length
+    // <= kLutBits) that a kLutBits-bit window p starts with, by the canonical
+    // limit test, as (L << 16) | symbol, or 0.  Then each entry chains up to
+    // three t1 lookups; a window with only r valid leading bits (the rest
+    // zero) still decodes a codeword of length <= r correctly, because such a
+    // codeword depends on its own bits only.
+    __shared__ uint32_t t1[1u << kLutBits];
+    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
+        uint32_t e = 0;
+        for (uint32_t l = 1; l <= (uint32_t)kLutBits; ++l) {
+            const uint64_t v = p >> (kLutBits - l);
+            if (cntL[l] && v < first[l] + cntL[l]) {
+                e = (l << 16) | perm(offs[l] + (uint32_t)(v - first[l]));
+                break;
+            }
+        }
+        t1[p] = e;
+    }
+    __syncthreads();
+    // Second level: number the prefixes that start a longer codeword, give
+    // each a block of 2^k entries resolving the next k bits.
+    __shared__ uint16_t lslot[1u << kLutBits];
+    __shared__ uint16_t lpref[1u << kLutBits];
+    __shared__ uint32_t s_wsum[kCbWaves];
+    constexpr uint32_t kPer = (1u << kLutBits) / kCb;
+    {
+        uint32_t c = 0;
+        for (uint32_t i = 0; i < kPer; ++i) c += t1[threadIdx.x * kPer + i] == 0;
+        const uint32_t inc = wave_incl_scan_u32(c);
+        if (lane_id() == kWave - 1) s_wsum[threadIdx.x / kWave] = inc;
+        __syncthreads();
+        uint32_t base = inc - c;
+        for (uint32_t v = 0; v < threadIdx.x / kWave; ++v) base += s_wsum[v];
+        for (uint32_t i = 0; i < kPer; ++i) {
+            const uint32_t p = threadIdx.x * kPer + i;
+            if (t1[p] == 0) {
+                lslot[p] = (uint16_t)base;
+                lpref[base] = (uint16_t)p;
+                ++base;
+            } else {
+                lslot[p] = 0xFFFF;
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t nlong = 0;
+    for (int v = 0; v < kCbWaves; ++v) nlong += s_wsum[v];
+    const uint32_t maxl = maxl_in;
+    uint32_t l2k = 0;
+    if (maxl > (uint32_t)kLutBits && nlong > 0) {
+        l2k = min(kL2MaxBits, maxl - (uint32_t)kLutBits);
+        while (l2k > 0 && (nlong << l2k) > kL2Size) --l2k;
+    }
+    const uint32_t l2n = l2k ? nlong << l2k : 0u;
+    for (uint32_t i = threadIdx.x; i < l2n; i += kCb) {
+        const uint32_t p = lpref[i >> l2k];
+        const uint64_t wv = ((uint64_t)p << l2k) | (i & ((1u << l2k) - 1));  // kLutBits + l2k bits
+        uint32_t e = 0;
+        for (uint32_t l = kLutBits + 1; l <= kLutBits + l2k; ++l) {
+            const uint64_t v = wv >> (kLutBits + l2k - l);
+            if (cntL[l] && v < first[l] + cntL[l]) {
+                e = (l << 16) | perm(offs[l] + (uint32_t)(v - first[l]));
+                break;
+            }
+        }
+        T->l2[i] = e;
+    }
+    if (threadIdx.x == 0) T->l2k = l2k, T->l2n = l2n;
+    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
+        uint64_t e = 0;
+        uint32_t pos = 0, n = 0;
+        while (n < 3 && pos < (uint32_t)kLutBits) {
+            const uint32_t v = t1[(p << pos) & ((1u << kLutBits) - 1)];
+            const uint32_t L = v >> 16;
+            if (L == 0 || L > (uint32_t)kLutBits - pos) break;
+            e |= (uint64_t)(v & 0xFFFFu) << (16 * n);
+            if (n < 2) e |= (uint64_t)L << (56 + 4 * n);
+            pos += L;
+            ++n;
+        }
+        if (n == 0) e = l2k && lslot[p] != 0xFFFF ? (uint64_t)lslot[p] << l2k : 0xFFFFull;
+        e |= (uint64_t)n << 48;
+        e |= (uint64_t)pos << 50;
+        T->lut[p] = e;
+    }
+}
+
 __global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
-                                                   uint8_t* __restrict__ tabs)
+                                                   uint8_t* __restrict__ tabs, size_t stride)
 {
     const FieldDesc& fd = F[blockIdx.x];
     EBC_G FieldDyn* dy = fd.dyn;
-    if (dy->status != ST_OK || !huff_codec(dy->codec)) return;
-    DecTab* T = (DecTab*)(tabs + (size_t)blockIdx.x * dectab_bytes());
+    if (dy->status != ST_OK || !huff_codec(dy->codec) || fd.n_bins > kMaxBins) return;
+    DecTab* T = (DecTab*)(tabs + (size_t)blockIdx.x * stride);
     const uint32_t nb = fd.n_bins;
     __shared__ uint8_t len_s[kMaxBins];
     __shared__ uint16_t cnt[(kMaxBins / 64) * 65 + 2];
@@ -448,111 +829,92 @@ __global__ __launch_bounds__(kCb) void k_dectab(const FieldDesc* __restrict__ F,
     }
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < nb; i += kCb) T->perm[i] = perm_s[i];
-    // left-aligned ends of the code space of lengths <= L (monotone in L)
     __syncthreads();
-    if (threadIdx.x <= 64) {
-        const uint32_t L = threadIdx.x;
-        const uint32_t maxl = s_maxl;
-        uint64_t endv = ~0ull;
-        if (L >= 1 && L < maxl) endv = (first[L] + cntL[L]) << (64 - L);
-        T->endv[L] = endv;
-    }
-    // Multi-symbol lookup table in two steps.  t1[p]: the codeword (length
-    // <= kLutBits) that a kLutBits-bit window p starts with, by the canonical
-    // limit test, as (L << 16) | symbol, or 0.  Then each entry chains up to
-    // three t1 lookups; a window with only r valid leading bits (the rest
-    // zero) still decodes a codeword of length <= r correctly, because such a
-    // codeword depends on its own bits only.
-    __shared__ uint32_t t1[1u << kLutBits];
-    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
-        uint32_t e = 0;
-        for (uint32_t l = 1; l <= (uint32_t)kLutBits; ++l) {
-            const uint64_t v = p >> (kLutBits - l);
-            if (cntL[l] && v < first[l] + cntL[l]) {
-                e = (l << 16) | perm_s[offs[l] + (uint32_t)(v - first[l])];
-                break;
-            }
-        }
-        t1[p] = e;
-    }
+    dectab_tables(T, cntL, first, offs, s_maxl, [&](uint32_t i) { return (uint32_t)perm_s[i]; });
+}
+
+// Decoder tables for wide bins (n_bins > kMaxBins): the same tables, with the
+// per-length counts taken by LDS atomics, the permutation written straight
+// to T->perm in blocks of kCb symbols (running per-length ranks) and read
+// back from there.
+__global__ __launch_bounds__(kCb) void k_dectab_wide(const FieldDesc* __restrict__ F,
+                                                        uint8_t* __restrict__ tabs, size_t stride)
+{
+    const FieldDesc& fd = F[blockIdx.x];
+    EBC_G FieldDyn* dy = fd.dyn;
+    if (dy->status != ST_OK || !huff_codec(dy->codec) || fd.n_bins <= kMaxBins) return;
+    DecTab* T = (DecTab*)(tabs + (size_t)blockIdx.x * stride);
+    const uint32_t nb = fd.n_bins;
+    __shared__ uint32_t cntL[65];
+    __shared__ uint64_t first[65];
+    __shared__ uint32_t offs[65];
+    __shared__ uint32_t run[65];
+    __shared__ uint32_t wc[kCbWaves][65];
+    __shared__ int s_bad;
+    __shared__ uint32_t s_maxl;
+    if (threadIdx.x < 65) cntL[threadIdx.x] = 0, run[threadIdx.x] = 0;
+    for (uint32_t i = threadIdx.x; i < kCbWaves * 65; i += kCb) (&wc[0][0])[i] = 0;
+    if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    // Second level: number the prefixes that start a longer codeword, give
-    // each a block of 2^k entries resolving the next k bits.
-    __shared__ uint16_t lslot[1u << kLutBits];
-    __shared__ uint16_t lpref[1u << kLutBits];
-    __shared__ uint32_t s_wsum[kCbWaves];
-    constexpr uint32_t kPer = (1u << kLutBits) / kCb;
-    {
-        uint32_t c = 0;
-        for (uint32_t i = 0; i < kPer; ++i) c += t1[threadIdx.x * kPer + i] == 0;
-        const uint32_t inc = wave_incl_scan_u32(c);
-        if (lane_id() == kWave - 1) s_wsum[threadIdx.x / kWave] = inc;
-        __syncthreads();
-        uint32_t base = inc - c;
-        for (uint32_t v = 0; v < threadIdx.x / kWave; ++v) base += s_wsum[v];
-        for (uint32_t i = 0; i < kPer; ++i) {
-            const uint32_t p = threadIdx.x * kPer + i;
-            if (t1[p] == 0) {
-                lslot[p] = (uint16_t)base;
-                lpref[base] = (uint16_t)p;
-                ++base;
-            } else {
-                lslot[p] = 0xFFFF;
-            }
-        }
+    const uint8_t* alen = fd.arc + kHdr;
+    for (uint32_t s = threadIdx.x; s < nb; s += kCb) {
+        const uint32_t L = alen[s];
+        if (L > kMaxDecodeLen) s_bad = 1;
+        else if (L) atomicAdd(&cntL[L], 1u);
     }
     __syncthreads();
-    uint32_t nlong = 0;
-    for (int v = 0; v < kCbWaves; ++v) nlong += s_wsum[v];
-    const uint32_t maxl = s_maxl;
-    uint32_t l2k = 0;
-    if (maxl > (uint32_t)kLutBits && nlong > 0) {
-        l2k = min(kL2MaxBits, maxl - (uint32_t)kLutBits);
-        while (l2k > 0 && (nlong << l2k) > kL2Size) --l2k;
+    if (s_bad) {
+        if (threadIdx.x == 0) dy->status = ST_ERR_ARCHIVE;
+        return;
     }
-    const uint32_t l2n = l2k ? nlong << l2k : 0u;
-    for (uint32_t i = threadIdx.x; i < l2n; i += kCb) {
-        const uint32_t p = lpref[i >> l2k];
-        const uint64_t wv = ((uint64_t)p << l2k) | (i & ((1u << l2k) - 1));  // kLutBits + l2k bits
-        uint32_t e = 0;
-        for (uint32_t l = kLutBits + 1; l <= kLutBits + l2k; ++l) {
-            const uint64_t v = wv >> (kLutBits + l2k - l);
-            if (cntL[l] && v < first[l] + cntL[l]) {
-                e = (l << 16) | perm_s[offs[l] + (uint32_t)(v - first[l])];
-                break;
-            }
+    if (threadIdx.x == 0) {
+        // canonical first codes; Kraft's inequality must hold at every length
+        uint64_t c = 0;
+        uint32_t off = 0, maxl = 0;
+        int bad = 0;
+        for (int L = 1; L <= 64; ++L) {
+            const uint32_t n = cntL[L];
+            first[L] = c;
+            offs[L] = off;
+            T->first[L] = c;
+            T->count[L] = n;
+            T->offset[L] = off;
+            off += n;
+            if (L <= kMaxDecodeLen && c + n > (1ull << L)) bad = 1;
+            c = L <= kMaxDecodeLen ? (c + n) << 1 : 0;
+            if (n) maxl = L;
         }
-        T->l2[i] = e;
+        T->first[0] = 0, T->count[0] = 0, T->offset[0] = 0;
+        T->max_len = maxl;
+        s_maxl = maxl;
+        if (maxl == 0 || bad) dy->status = ST_ERR_ARCHIVE;
+        s_bad = bad | (maxl == 0);
     }
-    if (threadIdx.x == 0) T->l2k = l2k, T->l2n = l2n;
-    for (uint32_t p = threadIdx.x; p < (1u << kLutBits); p += kCb) {
-        uint64_t e = 0;
-        uint32_t pos = 0, n = 0;
-        while (n < 3 && pos < (uint32_t)kLutBits) {
-            const uint32_t v = t1[(p << pos) & ((1u << kLutBits) - 1)];
-            const uint32_t L = v >> 16;
-            if (L == 0 || L > (uint32_t)kLutBits - pos) break;
-            e |= (uint64_t)(v & 0xFFFFu) << (16 * n);
-            if (n < 2) e |= (uint64_t)L << (56 + 4 * n);
-            pos += L;
-            ++n;
-        }
-        if (n == 0) e = l2k && lslot[p] != 0xFFFF ? (uint64_t)lslot[p] << l2k : 0xFFFFull;
-        e |= (uint64_t)n << 48;
-        e |= (uint64_t)pos << 50;
-        T->lut[p] = e;
+    __syncthreads();
+    if (s_bad) return;
+    for (uint32_t b0 = 0; b0 < nb; b0 += kCb) {
+        const uint32_t s = b0 + threadIdx.x;
+        const uint32_t L = s < nb ? alen[s] : 0u;
+        const uint32_t rk = blocked_rank(L, run, wc);
+        if (L) T->perm[offs[L] + rk] = (uint16_t)s;
     }
+    __syncthreads();
+    dectab_tables(T, cntL, first, offs, s_maxl, [&](uint32_t i) { return (uint32_t)T->perm[i]; });
 }
 
 hipError_t launch_codebook(const FieldDesc* F, int nf, uint32_t n_bins, int pass, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kCb), codebook_lds_bytes(n_bins), s, F, pass);
+    if (n_bins > kMaxBins) hipLaunchKernelGGL(k_codebook_wide, dim3(nf), dim3(kCb), 0, s, F, pass);
+    else hipLaunchKernelGGL(k_codebook, dim3(nf), dim3(kCb), codebook_lds_bytes(n_bins), s, F, pass);
     return hipGetLastError();
 }
 
-hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, hipStream_t s)
+hipError_t launch_dectab(const FieldDesc* F, int nf, uint8_t* tabs, size_t stride, uint32_t max_bins,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dectab, dim3(nf), dim3(kCb), 0, s, F, tabs);
+    // narrow and wide fields of one batch each skip the other kernel
+    hipLaunchKernelGGL(k_dectab, dim3(nf), dim3(kCb), 0, s, F, tabs, stride);
+    if (max_bins > kMaxBins) hipLaunchKernelGGL(k_dectab_wide, dim3(nf), dim3(kCb), 0, s, F, tabs, stride);
     return hipGetLastError();
 }
 

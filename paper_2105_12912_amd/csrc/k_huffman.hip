@@ -21,11 +21,16 @@ namespace ebc {
 
 size_t huff_write_lds_bytes(uint32_t n_bins, uint32_t hc)
 {
-    // code table, then per wave a word buffer of 2 * hc words (one pass of
-    // kPassHc symbols for longer chunks)
+    // code table (none for wide bins, whose table stays in HBM), then per
+    // wave a word buffer of 2 * hc words (one pass of kPassHc symbols for
+    // longer chunks)
     const uint32_t span = hc <= kPassHc ? hc : kPassHc;
-    return (size_t)n_bins * 8 + (size_t)huff_cpw(hc) * 2 * span * 4;
+    return (size_t)(n_bins > kMaxBins ? 0 : n_bins) * 8 + (size_t)huff_cpw(hc) * 2 * span * 4;
 }
+
+// The writer's table entry for symbol s (see write_entry), for wide bins
+// built from the codebook in HBM on every lookup.
+__device__ __forceinline__ uint64_t write_entry(uint64_t packed);
 
 // Symbols [lo, lo + S) of a chunk (S = hc / 64, owned by one lane), kept as
 // raw 16-byte blocks so that the loads can be issued one work unit ahead and
@@ -152,7 +157,8 @@ __device__ __forceinline__ void enc_pipeline(const FieldDesc* __restrict__ F, in
 // Both encode kernels are persistent: a workgroup walks groups of
 // huff_cpw(hc) chunks with a grid stride and reloads the code table in LDS
 // only when it moves to another field.
-template <uint32_t S>
+// W: wide bins (n_bins > kMaxBins), whose lengths are read from HBM
+template <uint32_t S, bool W>
 struct BitsProc {
     const FieldDesc* F;
     uint32_t* wcnt;
@@ -162,7 +168,7 @@ struct BitsProc {
     {
         if (!u.ok) return;
         const FieldDesc& fd = F[u.f];
-        if (u.f != cur) {
+        if (!W && u.f != cur) {
             __syncthreads();
             for (uint32_t s = threadIdx.x; s < fd.n_bins; s += kWave * huff_cpw(64 * S)) len_s[s] = fd.len[s];
             __syncthreads();
@@ -176,7 +182,7 @@ struct BitsProc {
         uint32_t bits = 0;
 #pragma unroll
         for (uint32_t k = 0; k < S; ++k) {
-            const uint32_t L = len_s[k < m ? r.at(k) : 0u];
+            const uint32_t L = W ? fd.len[k < m ? r.at(k) : 0u] : len_s[k < m ? r.at(k) : 0u];
             bits += k < m ? L : 0u;
         }
         bits = wave_sum_u32(bits);
@@ -187,13 +193,13 @@ struct BitsProc {
     }
 };
 
-template <uint32_t S>
+template <uint32_t S, bool W>
 __global__ __launch_bounds__(kBlock) void k_huff_bits(const FieldDesc* __restrict__ F, int nf,
                                                       uint32_t* __restrict__ wcnt, uint32_t units,
                                                       int which)
 {
-    __shared__ uint8_t len_s[kMaxBins];
-    BitsProc<S> proc{F, wcnt, len_s, -1};
+    __shared__ uint8_t len_s[W ? 1 : kMaxBins];
+    BitsProc<S, W> proc{F, wcnt, len_s, -1};
     enc_pipeline<S>(F, nf, units, which, proc);
 }
 
@@ -237,12 +243,16 @@ __device__ __forceinline__ void put_left(uint64_t& acc, uint32_t& nacc, uint32_t
     }
 }
 
-template <uint32_t S>
+template <uint32_t S, bool W>
 struct WriteProc {
     const FieldDesc* F;
     const uint32_t* woff;
     uint64_t* lds64;
     int cur;
+    __device__ __forceinline__ uint64_t entry(const FieldDesc& fd, const uint64_t* code_s, uint32_t sym) const
+    {
+        return W ? write_entry(fd.code[sym]) : code_s[sym];
+    }
     // up to 16 symbols per lane keep their table entries in registers between
     // the bit count and the packing; wider lanes look them up twice
     static constexpr bool kKeep = S <= 16;
@@ -257,8 +267,8 @@ struct WriteProc {
         // LDS accesses complete in order, so clearing, packing and copying
         // out need no barrier; only a new field's code table (shared by the
         // workgroup, whose waves all work on one field) does.
-        uint32_t* wbuf = (uint32_t*)(lds64 + nb) + (threadIdx.x / kWave) * 2 * hc;
-        if (u.f != cur) {
+        uint32_t* wbuf = (uint32_t*)(lds64 + (W ? 0 : nb)) + (threadIdx.x / kWave) * 2 * hc;
+        if (!W && u.f != cur) {
             __syncthreads();
             for (uint32_t s = threadIdx.x; s < nb; s += kWave * huff_cpw(64 * S))
                 code_s[s] = write_entry(fd.code[s]);
@@ -275,7 +285,7 @@ struct WriteProc {
         uint32_t mybits = 0, lmax = 0;
 #pragma unroll
         for (uint32_t k = 0; k < S; ++k) {
-            const uint64_t v0 = code_s[k < m ? r.at(k) : 0u];
+            const uint64_t v0 = entry(fd, code_s, k < m ? r.at(k) : 0u);
             const uint64_t v = k < m ? v0 : 0ull;
             if (kKeep) e[kKeep ? k : 0] = v;
             const uint32_t L = (uint32_t)v & 0xFFu;
@@ -296,13 +306,13 @@ struct WriteProc {
             if (!__any(lmax > 32)) {
 #pragma unroll
                 for (uint32_t k = 0; k < S; ++k) {
-                    const uint64_t v = kKeep ? e[kKeep ? k : 0] : (k < m ? code_s[r.at(k)] : 0ull);
+                    const uint64_t v = kKeep ? e[kKeep ? k : 0] : (k < m ? entry(fd, code_s, r.at(k)) : 0ull);
                     put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), (uint32_t)v & 0xFFu);
                 }
             } else {  // a codeword longer than 32 bits somewhere in the chunk
 #pragma unroll
                 for (uint32_t k = 0; k < S; ++k) {
-                    const uint64_t v = k < m ? code_s[r.at(k)] : 0ull;
+                    const uint64_t v = k < m ? entry(fd, code_s, r.at(k)) : 0ull;
                     const uint32_t L = (uint32_t)v & 0xFFu;
                     if (L <= 32) {
                         put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), L);
@@ -332,13 +342,13 @@ struct WriteProc {
     }
 };
 
-template <uint32_t S>
+template <uint32_t S, bool W>
 __global__ __launch_bounds__(kBlock) void k_huff_write(const FieldDesc* __restrict__ F, int nf,
                                                        const uint32_t* __restrict__ woff,
                                                        uint32_t units)
 {
     extern __shared__ uint64_t lds64[];
-    WriteProc<S> proc{F, woff, lds64, -1};
+    WriteProc<S, W> proc{F, woff, lds64, -1};
     enc_pipeline<S>(F, nf, units, 2, proc);
 }
 
@@ -369,17 +379,18 @@ __device__ __forceinline__ void load_pass(const EncUnit& u, uint64_t lo, uint32_
     }
 }
 
+template <bool W>
 __global__ __launch_bounds__(kWave) void k_huff_bits_long(const FieldDesc* __restrict__ F, int nf,
                                                           uint32_t* __restrict__ wcnt, uint32_t units,
                                                           int which)
 {
-    __shared__ uint8_t len_s[kMaxBins];
+    __shared__ uint8_t len_s[W ? 1 : kMaxBins];
     int cur = -1;
     for (uint32_t t = blockIdx.x; t < units; t += gridDim.x) {
         const EncUnit u = enc_unit<kPassPerLane>(F, nf, t, which);
         if (!u.ok) continue;
         const FieldDesc& fd = F[u.f];
-        if (u.f != cur) {
+        if (!W && u.f != cur) {
             for (uint32_t s = threadIdx.x; s < fd.n_bins; s += kWave) len_s[s] = fd.len[s];
             cur = u.f;
         }
@@ -392,7 +403,8 @@ __global__ __launch_bounds__(kWave) void k_huff_bits_long(const FieldDesc* __res
             load_pass(u, lo, sym);
             uint32_t b = 0;
 #pragma unroll
-            for (uint32_t k = 0; k < kPassPerLane; ++k) b += sym[k] == 0xFFFFFFFFu ? 0u : len_s[sym[k]];
+            for (uint32_t k = 0; k < kPassPerLane; ++k)
+                b += sym[k] == 0xFFFFFFFFu ? 0u : (W ? fd.len[sym[k]] : len_s[sym[k]]);
             bits += wave_sum_u32(b);
         }
         if (lane_id() == 0) {
@@ -402,6 +414,7 @@ __global__ __launch_bounds__(kWave) void k_huff_bits_long(const FieldDesc* __res
     }
 }
 
+template <bool W>
 __global__ __launch_bounds__(kWave) void k_huff_write_long(const FieldDesc* __restrict__ F, int nf,
                                                            const uint32_t* __restrict__ woff,
                                                            uint32_t units)
@@ -415,11 +428,12 @@ __global__ __launch_bounds__(kWave) void k_huff_write_long(const FieldDesc* __re
         const auto* dy = kconst(fd.dyn);
         const uint32_t nb = fd.n_bins;
         uint64_t* code_s = lds64;
-        uint32_t* wbuf = (uint32_t*)(lds64 + nb);
-        if (u.f != cur) {
+        uint32_t* wbuf = (uint32_t*)(lds64 + (W ? 0 : nb));
+        if (!W && u.f != cur) {
             for (uint32_t s = threadIdx.x; s < nb; s += kWave) code_s[s] = write_entry(fd.code[s]);
             cur = u.f;
         }
+        auto entry = [&](uint32_t sym) { return W ? write_entry(fd.code[sym]) : code_s[sym]; };
         if (u.c >= u.nch) continue;
         const uint32_t wo = woff[fd.hch_base + u.c] - woff[fd.hch_base];
         EBC_G uint32_t* dst = (EBC_G uint32_t*)(fd.arc + dy->off_words) + wo;
@@ -435,7 +449,7 @@ __global__ __launch_bounds__(kWave) void k_huff_write_long(const FieldDesc* __re
             uint32_t mybits = 0;
 #pragma unroll
             for (uint32_t k = 0; k < kPassPerLane; ++k)
-                mybits += sym[k] == 0xFFFFFFFFu ? 0u : (uint32_t)code_s[sym[k]] & 0xFFu;
+                mybits += sym[k] == 0xFFFFFFFFu ? 0u : (uint32_t)entry(sym[k]) & 0xFFu;
             const uint32_t incl = wave_incl_scan_u32(mybits);
             const uint32_t pass_bits = (uint32_t)__shfl((int)incl, kWave - 1);
             // sub-chunk counts: 4 lanes of 64 symbols per 256-symbol sub-chunk
@@ -455,7 +469,7 @@ __global__ __launch_bounds__(kWave) void k_huff_write_long(const FieldDesc* __re
 #pragma unroll
             for (uint32_t k = 0; k < kPassPerLane; ++k) {
                 if (sym[k] == 0xFFFFFFFFu) continue;
-                const uint64_t v = code_s[sym[k]];
+                const uint64_t v = entry(sym[k]);
                 const uint32_t L = (uint32_t)v & 0xFFu;
                 if (L <= 32) {
                     put_left(acc, nacc, w, wbuf, (uint32_t)(v >> 32), L);
@@ -588,8 +602,9 @@ struct LongCode {
 // until the slower lanes have caught up, which never delays the wave: the
 // waiting lane is ahead of the slowest one.
 constexpr uint32_t kFlush = 32;
-constexpr uint32_t kCap = 46;                     // symbols a row holds; a step needs 3 free slots
-constexpr uint32_t kStageWords = 25;              // row stride (odd): kCap + 3 slots and more
+constexpr uint32_t kCap = kFlush + 14;            // symbols a row holds; a step needs 3 free slots
+constexpr uint32_t kStageWords = ((kCap + 4) / 2) | 1;  // row stride (odd): kCap + 3 slots and more
+constexpr uint32_t kParts = kFlush / 8;           // 16-byte pieces of a flushed block
 constexpr uint32_t kCheckEvery = 4;               // steps between flush checks
 static_assert(2 * kStageWords >= kCap + 3, "the three slots of a step stay inside the row");
 static_assert(kCap - 2 > kFlush, "a waiting lane always holds a whole block");
@@ -674,6 +689,30 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
     bool slow = false;
     bool act = want > 0;
     uint32_t nxt = wr.peek();
+    // a block of kFlush symbols leaves when every lane still decoding has one
+    auto flush = [&]() {
+        if (__all(sp >= kFlush || !act)) {
+#pragma unroll
+            for (uint32_t k = 0; k < kParts; ++k) {
+                const uint32_t piece = k * kWave + lane;
+                const uint32_t L = piece / kParts, part = piece % kParts;
+                const uint32_t spL = (uint32_t)__shfl((int)sp, (int)L);
+                const uint32_t flL = (uint32_t)__shfl((int)flushed, (int)L);
+                if (spL >= kFlush) {
+                    const uint32_t* src = wave_rows + L * kStageWords + part * 4;
+                    const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
+                    *(EBC_G uint4*)(fd.hsym + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
+                }
+            }
+            if (sp >= kFlush) {
+                // the symbols past the block move to the front of the row
+#pragma unroll
+                for (uint32_t w = 0; w < kStageWords - kFlush / 2; ++w) row[w] = row[kFlush / 2 + w];
+                sp -= kFlush;
+                flushed += kFlush;
+            }
+        }
+    };
     while (__any(act)) {
         wr.refill();
 #pragma unroll
@@ -727,28 +766,7 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
             valid -= tl;
             act = act && j < want;
         }
-        // a block of kFlush symbols leaves when every lane still decoding has one
-        if (__all(sp >= kFlush || !act)) {
-#pragma unroll
-            for (uint32_t k = 0; k < 4; ++k) {
-                const uint32_t piece = k * kWave + lane;
-                const uint32_t L = piece >> 2, part = piece & 3;
-                const uint32_t spL = (uint32_t)__shfl((int)sp, (int)L);
-                const uint32_t flL = (uint32_t)__shfl((int)flushed, (int)L);
-                if (spL >= kFlush) {
-                    const uint32_t* src = wave_rows + L * kStageWords + part * 4;
-                    const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
-                    *(EBC_G uint4*)(fd.hsym + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
-                }
-            }
-            if (sp >= kFlush) {
-                // the symbols past the block move to the front of the row
-#pragma unroll
-                for (uint32_t w = 0; w < kStageWords - kFlush / 2; ++w) row[w] = row[kFlush / 2 + w];
-                sp -= kFlush;
-                flushed += kFlush;
-            }
-        }
+        flush();
     }
     // exact path, one codeword at a time from a window read straight from the
     // stream (lanes that met a codeword longer than 32 bits)
@@ -819,15 +837,15 @@ __global__ __launch_bounds__(kBlock) void k_huff_prep(const FieldDesc* __restric
     wcnt[fd.hch_base + c] = (run + 31) / 32;
 }
 
-#define EBC_HC_DISPATCH(KERNEL, ...)                                                        \
+#define EBC_HC_DISPATCH(KERNEL, W, ...)                                                     \
     switch (hc) {                                                                           \
-    case 64: hipLaunchKernelGGL(KERNEL<1>, __VA_ARGS__); break;                             \
-    case 128: hipLaunchKernelGGL(KERNEL<2>, __VA_ARGS__); break;                            \
-    case 256: hipLaunchKernelGGL(KERNEL<4>, __VA_ARGS__); break;                            \
-    case 512: hipLaunchKernelGGL(KERNEL<8>, __VA_ARGS__); break;                            \
-    case 1024: hipLaunchKernelGGL(KERNEL<16>, __VA_ARGS__); break;                          \
-    case 2048: hipLaunchKernelGGL(KERNEL<32>, __VA_ARGS__); break;                          \
-    case 4096: hipLaunchKernelGGL(KERNEL<64>, __VA_ARGS__); break;                          \
+    case 64: hipLaunchKernelGGL((KERNEL<1, W>), __VA_ARGS__); break;                        \
+    case 128: hipLaunchKernelGGL((KERNEL<2, W>), __VA_ARGS__); break;                       \
+    case 256: hipLaunchKernelGGL((KERNEL<4, W>), __VA_ARGS__); break;                       \
+    case 512: hipLaunchKernelGGL((KERNEL<8, W>), __VA_ARGS__); break;                       \
+    case 1024: hipLaunchKernelGGL((KERNEL<16, W>), __VA_ARGS__); break;                     \
+    case 2048: hipLaunchKernelGGL((KERNEL<32, W>), __VA_ARGS__); break;                     \
+    case 4096: hipLaunchKernelGGL((KERNEL<64, W>), __VA_ARGS__); break;                     \
     default: return hipErrorInvalidValue;                                                   \
     }
 
@@ -851,17 +869,23 @@ hipError_t launch_words_check(const FieldDesc* F, int nf, const uint32_t* woff, 
 // persistent grid: enough workgroups to fill the device several times over
 static uint32_t persistent_grid(uint32_t units) { return units < kPersistentBlocks ? units : kPersistentBlocks; }
 
-hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t* wcnt,
-                            int which, hipStream_t s)
+hipError_t launch_huff_bits(const FieldDesc* F, int nf, uint32_t units, uint32_t hc, uint32_t n_bins,
+                            uint32_t* wcnt, int which, hipStream_t s)
 {
     if (!units) return hipSuccess;
+    const bool wide = n_bins > kMaxBins;
+    const dim3 g(persistent_grid(units));
     if (hc > kPassHc) {
-        hipLaunchKernelGGL(k_huff_bits_long, dim3(persistent_grid(units)), dim3(kWave), 0, s, F, nf, wcnt,
-                           units, which);
+        if (wide) hipLaunchKernelGGL(k_huff_bits_long<true>, g, dim3(kWave), 0, s, F, nf, wcnt, units, which);
+        else hipLaunchKernelGGL(k_huff_bits_long<false>, g, dim3(kWave), 0, s, F, nf, wcnt, units, which);
         return hipGetLastError();
     }
-    EBC_HC_DISPATCH(k_huff_bits, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)), 0, s, F, nf,
-                    wcnt, units, which)
+    const dim3 b(kWave * huff_cpw(hc));
+    if (wide) {
+        EBC_HC_DISPATCH(k_huff_bits, true, g, b, 0, s, F, nf, wcnt, units, which)
+    } else {
+        EBC_HC_DISPATCH(k_huff_bits, false, g, b, 0, s, F, nf, wcnt, units, which)
+    }
     return hipGetLastError();
 }
 
@@ -869,13 +893,20 @@ hipError_t launch_huff_write(const FieldDesc* F, int nf, uint32_t units, uint32_
                              uint32_t n_bins, const uint32_t* woff, hipStream_t s)
 {
     if (!units) return hipSuccess;
+    const bool wide = n_bins > kMaxBins;
+    const dim3 g(persistent_grid(units));
+    const size_t sh = huff_write_lds_bytes(n_bins, hc);
     if (hc > kPassHc) {
-        hipLaunchKernelGGL(k_huff_write_long, dim3(persistent_grid(units)), dim3(kWave),
-                           huff_write_lds_bytes(n_bins, hc), s, F, nf, woff, units);
+        if (wide) hipLaunchKernelGGL(k_huff_write_long<true>, g, dim3(kWave), sh, s, F, nf, woff, units);
+        else hipLaunchKernelGGL(k_huff_write_long<false>, g, dim3(kWave), sh, s, F, nf, woff, units);
         return hipGetLastError();
     }
-    EBC_HC_DISPATCH(k_huff_write, dim3(persistent_grid(units)), dim3(kWave * huff_cpw(hc)),
-                    huff_write_lds_bytes(n_bins, hc), s, F, nf, woff, units)
+    const dim3 b(kWave * huff_cpw(hc));
+    if (wide) {
+        EBC_HC_DISPATCH(k_huff_write, true, g, b, sh, s, F, nf, woff, units)
+    } else {
+        EBC_HC_DISPATCH(k_huff_write, false, g, b, sh, s, F, nf, woff, units)
+    }
     return hipGetLastError();
 }
 

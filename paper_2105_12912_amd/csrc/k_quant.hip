@@ -320,6 +320,8 @@ struct QuantCtx {
     double inv;
     int32_t r;
     uint32_t center;  // private count of the centre bin r (the dominant code)
+    uint32_t lo;      // wide bins: first code of the LDS window (slot 1)
+    EBC_G uint32_t* ghist;  // wide bins: the field histogram, for codes outside the window
 };
 
 // prequant one quad: d = rint(x * inv) in fp64 (Sec. IV-A.1)
@@ -336,6 +338,11 @@ template <> __device__ __forceinline__ const EBC_G double* field_in<double>(cons
 
 // postquant one quad of deltas: code, outlier scratch, histogram.
 // Returns a 4-bit mask of outliers among the valid elements.
+// WIDE (n_bins > kMaxBins): LDS slot 0 counts code 0, slots 1 .. kHistWin-1
+// the codes lo .. lo + kHistWin - 2 around the centre; any other code is
+// counted straight into the field histogram in HBM (rare for a predictable
+// field, whose deltas cluster around zero).
+template <bool WIDE>
 __device__ __forceinline__ uint32_t postquant4(const int32_t dl[4], int nvalid, QuantCtx& qc,
                                                uint32_t c[4], EBC_G int32_t* __restrict__ dsc,
                                                uint64_t i, uint32_t* sh_hist)
@@ -350,8 +357,18 @@ __device__ __forceinline__ uint32_t postquant4(const int32_t dl[4], int nvalid, 
                 om |= 1u << k;
                 dsc[i + k] = dl[k];
             }
-            if (c[k] == (uint32_t)qc.r) qc.center++;
-            else atomicAdd(&sh_hist[c[k]], 1u);
+            if (c[k] == (uint32_t)qc.r) {
+                qc.center++;
+            } else if (!WIDE) {
+                atomicAdd(&sh_hist[c[k]], 1u);
+            } else {
+                // slot 1 + (c - lo) for lo <= c < lo + kHistWin - 1 (unsigned
+                // difference: codes below lo wrap to large values)
+                const uint32_t dj = c[k] - qc.lo;
+                if (c[k] == 0) atomicAdd(&sh_hist[0], 1u);
+                else if (dj < kHistWin - 1) atomicAdd(&sh_hist[dj + 1], 1u);
+                else atomicAdd(&qc.ghist[c[k]], 1u);
+            }
         }
     }
     return om;
@@ -371,7 +388,7 @@ __device__ __forceinline__ uint32_t row_count(uint32_t om, uint64_t rowmask)
 
 // One workgroup tile: quantise, record outliers, count codes into the LDS
 // histogram and outlier counts per row segment into `s_cnt` (2D/3D).
-template <int RANK, bool VEC, class T>
+template <int RANK, bool VEC, class T, bool WIDE>
 __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl, QuantCtx& qc,
                                                uint32_t* sh_hist, uint32_t* s_cnt,
                                                uint32_t* __restrict__ segs)
@@ -404,7 +421,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
                 if (l == 0) left = 0;
                 dl[0] = d[0] - left, dl[1] = d[1] - d[0], dl[2] = d[2] - d[1], dl[3] = d[3] - d[2];
                 uint32_t code[4];
-                const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
+                const uint32_t om = postquant4<WIDE>(dl, nv, qc, code, dsc, i0, sh_hist);
                 if (VEC && nv == 4) store_codes<true>(qo, i0, 4, code);
                 else store_codes<false>(qo, i0, nv, code);
                 const uint32_t cnt = row_count(om, ~0ull);
@@ -462,7 +479,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
                     fprev[k] = fy;
                 }
                 uint32_t code[4];
-                const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
+                const uint32_t om = postquant4<WIDE>(dl, nv, qc, code, dsc, i0, sh_hist);
                 store_codes<VEC>(qo, i0, nv, code);
                 const uint32_t cnt = row_count(om, rowmask);
                 if (xq == 0 && cnt) atomicAdd(&s_cnt[wyi * 64 + iz * 8 + y], cnt);
@@ -496,7 +513,7 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
 #pragma unroll
                 for (int k = 0; k < 4; ++k) dl[k] = e[k] - dpp_keep(dpp_shr<1>(e[k]));  // y = 0 reads 0
                 uint32_t code[4];
-                const uint32_t om = postquant4(dl, nv, qc, code, dsc, i0, sh_hist);
+                const uint32_t om = postquant4<WIDE>(dl, nv, qc, code, dsc, i0, sh_hist);
                 store_codes<VEC>(qo, i0, nv, code);
                 rowcnt += row_count(om, rowmask);
             }
@@ -508,13 +525,14 @@ __device__ __forceinline__ void construct_tile(const FieldDesc& fd, uint32_t tl,
 // Flush the LDS histogram of field `fd` into its partial row for this
 // workgroup and clear it.  Row (b - wg_base) mod G is unique per workgroup b
 // of the grid G among those that visit the field.
+template <bool WIDE>
 __device__ __forceinline__ void flush_hist(const FieldDesc& fd, QuantCtx& qc, uint32_t* sh_hist)
 {
     const uint32_t cs = wave_sum_u32(qc.center);
     qc.center = 0;
-    if (lane_id() == 0 && cs) atomicAdd(&sh_hist[qc.r], cs);
+    if (lane_id() == 0 && cs) atomicAdd(&sh_hist[WIDE ? (uint32_t)qc.r - qc.lo + 1u : (uint32_t)qc.r], cs);
     __syncthreads();
-    const uint32_t G = gridDim.x, nb = fd.n_bins;
+    const uint32_t G = gridDim.x, nb = hist_slots(fd.n_bins);
     const uint32_t row = (blockIdx.x + G - fd.wg_base % G) % G;
     EBC_G uint32_t* hp = fd.hpart + (uint64_t)row * nb;
     for (uint32_t b = threadIdx.x; b < nb; b += kBlock) {
@@ -527,14 +545,14 @@ __device__ __forceinline__ void flush_hist(const FieldDesc& fd, QuantCtx& qc, ui
 // Persistent over the workgroup tiles of one (rank, layout) group: the grid
 // strides over the tiles, so each workgroup visits every field in one run of
 // consecutive tiles and flushes one partial histogram per field it visits.
-template <int RANK, bool VEC, class T>
+template <int RANK, bool VEC, class T, bool WIDE>
 __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restrict__ F, int nf,
                                                       uint32_t n_tiles, uint32_t* __restrict__ seg_cnt)
 {
     extern __shared__ uint32_t sh_hist[];
     __shared__ uint32_t s_cnt[2][kWavesPerBlock * 64];  // outliers per row, double-buffered
     const uint32_t nb = F[0].n_bins;
-    for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh_hist[b] = 0;
+    for (uint32_t b = threadIdx.x; b < hist_slots(nb); b += kBlock) sh_hist[b] = 0;
     s_cnt[0][threadIdx.x] = 0;
     s_cnt[1][threadIdx.x] = 0;
     __syncthreads();
@@ -547,14 +565,16 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
         const auto* dy = kconst(fd.dyn);  // scalar loads: no wait on the previous tile's stores
         if (dy->status != ST_OK || dy->codec == ARC_CONST) continue;  // uniform over the workgroup
         if (f != cur) {
-            if (cur >= 0) flush_hist(F[cur], qc, sh_hist);
+            if (cur >= 0) flush_hist<WIDE>(F[cur], qc, sh_hist);
             cur = f;
             qc.inv = dy->inv;
             qc.r = (int32_t)(nb / 2);
+            qc.lo = hist_win_lo(nb);
+            qc.ghist = fd.hist;
         }
         const uint32_t tl = t - fd.wg_base;
         uint32_t* cnt = s_cnt[par];
-        construct_tile<RANK, VEC, T>(fd, tl, qc, sh_hist, cnt, seg_cnt + fd.seg_base);
+        construct_tile<RANK, VEC, T, WIDE>(fd, tl, qc, sh_hist, cnt, seg_cnt + fd.seg_base);
         if (RANK >= 2) {
             __syncthreads();
             // one outlier count per row segment of this tile; the buffer is
@@ -576,12 +596,14 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
             par ^= 1;
         }
     }
-    if (cur >= 0) flush_hist(F[cur], qc, sh_hist);
+    if (cur >= 0) flush_hist<WIDE>(F[cur], qc, sh_hist);
 }
 
 // ------------------------------------------------------ histogram reduce
-// grid (ceil(n_bins / 256), kHistSplit, nf): split the partial rows of a
-// field over kHistSplit workgroups, then add into the field histogram.
+// grid (ceil(slots / 256), kHistSplit, nf): split the partial rows of a
+// field over kHistSplit workgroups, then add into the field histogram (for
+// wide bins, slot j holds code 0 or code lo + j - 1; the codes outside the
+// window were already counted there by construction).
 constexpr int kHistSplit = 64;
 __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restrict__ F)
 {
@@ -589,12 +611,13 @@ __global__ __launch_bounds__(kBlock) void k_hist_reduce(const FieldDesc* __restr
     const auto* dy = kconst(fd.dyn);
     if (dy->status != ST_OK || dy->codec == ARC_CONST) return;
     const uint32_t b = blockIdx.x * kBlock + threadIdx.x;
-    if (b >= fd.n_bins) return;
-    const uint32_t nb = fd.n_bins;
+    const uint32_t nb = hist_slots(fd.n_bins);
+    if (b >= nb) return;
     uint32_t s = 0;
 #pragma unroll 8
     for (uint32_t r = blockIdx.y; r < fd.hrows; r += kHistSplit) s += fd.hpart[(uint64_t)r * nb + b];
-    if (s) atomicAdd(&fd.hist[b], s);
+    const uint32_t code = fd.n_bins > kMaxBins && b != 0 ? hist_win_lo(fd.n_bins) + b - 1 : b;
+    if (s) atomicAdd(&fd.hist[code], s);
 }
 
 // ------------------------------------------------------------- launchers
@@ -612,17 +635,17 @@ hipError_t launch_params(const FieldDesc* F, int nf, hipStream_t s)
     return hipGetLastError();
 }
 
-template <class T>
+template <class T, bool W>
 static hipError_t occupancy(int rank, bool vec, size_t sh, int* per)
 {
     if (rank == 1)
-        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, true, T>, kBlock, sh)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, false, T>, kBlock, sh);
+        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, true, T, W>, kBlock, sh)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<1, false, T, W>, kBlock, sh);
     if (rank == 2)
-        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, true, T>, kBlock, sh)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, false, T>, kBlock, sh);
-    return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, true, T>, kBlock, sh)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, false, T>, kBlock, sh);
+        return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, true, T, W>, kBlock, sh)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<2, false, T, W>, kBlock, sh);
+    return vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, true, T, W>, kBlock, sh)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_construct<3, false, T, W>, kBlock, sh);
 }
 
 // Workgroups of one construction variant that the device holds at once (the
@@ -632,26 +655,30 @@ uint32_t construct_resident_blocks(int rank, bool vec, uint32_t n_bins, bool f64
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const size_t sh = (size_t)n_bins * sizeof(uint32_t);
-    const hipError_t e = f64 ? occupancy<double>(rank, vec, sh, &per) : occupancy<float>(rank, vec, sh, &per);
+    const size_t sh = (size_t)hist_slots(n_bins) * sizeof(uint32_t);
+    const bool w = n_bins > kMaxBins;
+    const hipError_t e = f64 ? (w ? occupancy<double, true>(rank, vec, sh, &per)
+                                  : occupancy<double, false>(rank, vec, sh, &per))
+                             : (w ? occupancy<float, true>(rank, vec, sh, &per)
+                                  : occupancy<float, false>(rank, vec, sh, &per));
     if (e != hipSuccess || per <= 0 || cus <= 0) return 0;
     return (uint32_t)(per * cus);
 }
 
-template <class T>
+template <class T, bool W>
 static void construct_launch(const FieldDesc* F, int nf, int rank, bool vec, uint32_t wg_tiles,
                              dim3 g, size_t sh, uint32_t* seg_cnt, hipStream_t s)
 {
     const dim3 b(kBlock);
     if (rank == 1) {
-        if (vec) hipLaunchKernelGGL((k_construct<1, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<1, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<1, true, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<1, false, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     } else if (rank == 2) {
-        if (vec) hipLaunchKernelGGL((k_construct<2, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<2, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<2, true, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<2, false, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     } else {
-        if (vec) hipLaunchKernelGGL((k_construct<3, true, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
-        else hipLaunchKernelGGL((k_construct<3, false, T>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        if (vec) hipLaunchKernelGGL((k_construct<3, true, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
+        else hipLaunchKernelGGL((k_construct<3, false, T, W>), g, b, sh, s, F, nf, wg_tiles, seg_cnt);
     }
 }
 
@@ -659,15 +686,21 @@ hipError_t launch_construct(const FieldDesc* F, int nf, int rank, bool vec, bool
                             uint32_t blocks, uint32_t n_bins, uint32_t* seg_cnt, hipStream_t s)
 {
     if (wg_tiles == 0) return hipSuccess;
-    const size_t sh = (size_t)n_bins * sizeof(uint32_t);
-    if (f64) construct_launch<double>(F, nf, rank, vec, wg_tiles, dim3(blocks), sh, seg_cnt, s);
-    else construct_launch<float>(F, nf, rank, vec, wg_tiles, dim3(blocks), sh, seg_cnt, s);
+    const size_t sh = (size_t)hist_slots(n_bins) * sizeof(uint32_t);
+    const dim3 g(blocks);
+    if (n_bins > kMaxBins) {
+        if (f64) construct_launch<double, true>(F, nf, rank, vec, wg_tiles, g, sh, seg_cnt, s);
+        else construct_launch<float, true>(F, nf, rank, vec, wg_tiles, g, sh, seg_cnt, s);
+    } else {
+        if (f64) construct_launch<double, false>(F, nf, rank, vec, wg_tiles, g, sh, seg_cnt, s);
+        else construct_launch<float, false>(F, nf, rank, vec, wg_tiles, g, sh, seg_cnt, s);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_hist_reduce(const FieldDesc* F, int nf, uint32_t n_bins, hipStream_t s)
 {
-    dim3 g((n_bins + kBlock - 1) / kBlock, kHistSplit, nf);
+    dim3 g((hist_slots(n_bins) + kBlock - 1) / kBlock, kHistSplit, nf);
     hipLaunchKernelGGL(k_hist_reduce, g, dim3(kBlock), 0, s, F);
     return hipGetLastError();
 }

@@ -170,14 +170,27 @@ __global__ __launch_bounds__(kBlock) void k_rle_vhist(const FieldDesc* __restric
             t = skip_field(fd, t) - gridDim.x;
             continue;
         }
-        const uint32_t nb = fd.n_bins;
-        for (uint32_t b = threadIdx.x; b < nb; b += kBlock) sh[b] = 0;
+        // wide bins: LDS slots as in construction (code 0, then a window
+        // around the centre), other values counted in HBM directly
+        const uint32_t nb = fd.n_bins, ns = hist_slots(nb), wlo = hist_win_lo(nb);
+        const bool wide = nb > kMaxBins;
+        for (uint32_t b = threadIdx.x; b < ns; b += kBlock) sh[b] = 0;
         __syncthreads();
         const uint64_t hi = min(lo + (uint64_t)kRleTile, R);
-        for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&sh[fd.vsym[i]], 1u);
+        for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+            const uint32_t v = fd.vsym[i];
+            if (!wide) {
+                atomicAdd(&sh[v], 1u);
+            } else {
+                const uint32_t dj = v - wlo;  // codes below the window wrap to large values
+                if (v == 0) atomicAdd(&sh[0], 1u);
+                else if (dj < kHistWin - 1) atomicAdd(&sh[dj + 1], 1u);
+                else atomicAdd(&fd.vhist[v], 1u);
+            }
+        }
         __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nb; b += kBlock)
-            if (sh[b]) atomicAdd(&fd.vhist[b], sh[b]);
+        for (uint32_t b = threadIdx.x; b < ns; b += kBlock)
+            if (sh[b]) atomicAdd(&fd.vhist[wide && b ? wlo + b - 1 : b], sh[b]);
         __syncthreads();
     }
 }
@@ -234,12 +247,37 @@ __global__ __launch_bounds__(kBlock) void k_rle_check(const FieldDesc* __restric
     if (bad) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
 }
 
+// After the check: the run that holds the first element of every output
+// tile (the largest r with start[r] <= tile start), one thread per tile, so
+// that every tile's search is in flight at once rather than one thread per
+// workgroup searching while the others wait.
+__global__ __launch_bounds__(kBlock) void k_rle_tilemap(const FieldDesc* __restrict__ F, int nf,
+                                                        uint32_t units, const uint32_t* __restrict__ starts,
+                                                        uint32_t* __restrict__ tmap)
+{
+    const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= units) return;
+    const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
+    const FieldDesc& fd = F[f];
+    if (fd.dyn->status != ST_OK || !rle_codec(fd.codec_hdr)) return;
+    const uint32_t* S = starts + fd.rle_base;
+    const uint32_t s0 = S[0];
+    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    uint32_t a = 0, b = fd.n_runs_hdr - 1;
+    while (a < b) {
+        const uint32_t m = (a + b + 1) >> 1;
+        if ((uint64_t)(S[m] - s0) <= lo) a = m;
+        else b = m - 1;
+    }
+    tmap[t] = a;
+}
+
 __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restrict__ F, int nf,
-                                                       const uint32_t* __restrict__ starts)
+                                                       const uint32_t* __restrict__ starts,
+                                                       const uint32_t* __restrict__ tmap)
 {
     __shared__ uint32_t s_start[kRleTile + 1];
     __shared__ uint16_t s_val[kRleTile + 1];
-    __shared__ uint32_t s_rlo, s_nr;
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
@@ -250,25 +288,15 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     const uint32_t R = fd.n_runs_hdr;
     const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
     const uint64_t hi = min(lo + (uint64_t)kRleTile, fd.n);
-    if (threadIdx.x == 0) {
-        // largest r with start[r] <= lo, and largest r with start[r] <= hi - 1
-        uint32_t a = 0, b = R - 1;
-        while (a < b) {
-            const uint32_t m = (a + b + 1) >> 1;
-            if ((uint64_t)(S[m] - s0) <= lo) a = m;
-            else b = m - 1;
-        }
-        uint32_t c = a, d = R - 1;
-        while (c < d) {
-            const uint32_t m = (c + d + 1) >> 1;
-            if ((uint64_t)(S[m] - s0) <= hi - 1) c = m;
-            else d = m - 1;
-        }
-        s_rlo = a;
-        s_nr = c - a + 1;
+    // first run of this tile; its last run is the next tile's first, unless
+    // that one starts exactly at the next tile
+    const uint32_t rlo = tmap[t];
+    uint32_t rlast = R - 1;
+    if (t + 1 < fd.rt_base + fd.n_rt) {
+        const uint32_t r2 = tmap[t + 1];
+        rlast = (uint64_t)(S[r2] - s0) <= hi - 1 ? r2 : r2 - 1;
     }
-    __syncthreads();
-    const uint32_t rlo = s_rlo, nr = s_nr;  // nr <= kRleTile because every run is non-empty
+    const uint32_t nr = rlast - rlo + 1;  // <= kRleTile because every run is non-empty
     const EBC_G uint16_t* val = fd.rval;
     for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
         s_start[i] = S[rlo + i] - s0;
@@ -332,7 +360,7 @@ hipError_t launch_rle_vle_prep(const FieldDesc* F, int nf, uint32_t units, const
     e = launch_rle_write(F, nf, units, roff, kRleValSym, s);
     if (e != hipSuccess) return e;
     const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
-    hipLaunchKernelGGL(k_rle_vhist, dim3(g), dim3(kBlock), (size_t)n_bins * 4, s, F, nf, units);
+    hipLaunchKernelGGL(k_rle_vhist, dim3(g), dim3(kBlock), (size_t)hist_slots(n_bins) * 4, s, F, nf, units);
     return hipGetLastError();
 }
 
@@ -344,15 +372,19 @@ hipError_t launch_rle_len(const FieldDesc* F, int nf, uint32_t max_units, hipStr
 }
 
 hipError_t launch_rle_decode(const FieldDesc* F, int nf, uint32_t rl_units, uint32_t rt_units,
-                             uint32_t* starts, uint32_t* tmp, uint32_t n_starts, uint32_t scan_direct,
-                             hipStream_t s)
+                             uint32_t* starts, uint32_t* tmap, uint32_t* tmp, uint32_t n_starts,
+                             uint32_t scan_direct, hipStream_t s)
 {
     if (!rl_units) return hipSuccess;
     hipLaunchKernelGGL(k_rle_prep, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
     hipError_t e = launch_scan(starts, n_starts, tmp, s, scan_direct);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rle_check, dim3(rl_units), dim3(kBlock), 0, s, F, nf, starts);
-    if (rt_units) hipLaunchKernelGGL(k_rle_expand, dim3(rt_units), dim3(kBlock), 0, s, F, nf, starts);
+    if (rt_units) {
+        hipLaunchKernelGGL(k_rle_tilemap, dim3((rt_units + kBlock - 1) / kBlock), dim3(kBlock), 0, s, F, nf,
+                           rt_units, starts, tmap);
+        hipLaunchKernelGGL(k_rle_expand, dim3(rt_units), dim3(kBlock), 0, s, F, nf, starts, tmap);
+    }
     return hipGetLastError();
 }
 

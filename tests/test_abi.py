@@ -46,16 +46,19 @@ def test_param_validation(L):
     cases = [
         (ebc.make_params(0.0), -3), (ebc.make_params(float("inf")), -3),
         (ebc.make_params(1e-4, n_bins=3), -5), (ebc.make_params(1e-4, n_bins=70000), -5),
-        (ebc.make_params(1e-4, n_bins=8192), -11), (ebc.make_params(1e-4, huff_chunk=100), -1),
+        (ebc.make_params(1e-4, n_bins=65538), -5), (ebc.make_params(1e-4, huff_chunk=100), -1),
         (ebc.make_params(1e-4, huff_chunk=131072), -1),
     ]
     for p, want in cases:
         with pytest.raises(ebc.EbcError) as ei:
             ebc.ebc_compress_workspace_size(2, (16, 16), p)
         assert ei.value.status == want
-    # every power-of-two Huffman chunk from 64 to 65536 is implemented
+    # every power-of-two Huffman chunk from 64 to 65536 and every even bin
+    # count from 4 to 65536 is implemented
     for hc in (64, 4096, 8192, 65536):
         assert ebc.ebc_compress_workspace_size(2, (16, 16), ebc.make_params(1e-4, huff_chunk=hc)) > 0
+    for nb in (4, 4096, 4098, 8192, 65536):
+        assert ebc.ebc_compress_workspace_size(2, (16, 16), ebc.make_params(1e-4, n_bins=nb)) > 0
     for rank, dims, want in [(4, (2, 2, 2), -2), (2, (16, 0), -2), (1, (5, 2), -2),
                              (3, (1 << 16, 1 << 16, 2), -2)]:
         with pytest.raises(ebc.EbcError) as ei:
@@ -72,7 +75,8 @@ def test_host_side_rejections_need_no_device(L):
 
 
 def test_compress_bound_matches_oracle(L):
-    for rank, dims, nb in [(1, (1000003,), 1024), (2, (3600, 1800), 1024), (3, (33, 17, 9), 64)]:
+    for rank, dims, nb in [(1, (1000003,), 1024), (2, (3600, 1800), 1024), (3, (33, 17, 9), 64),
+                           (2, (300, 256), 65536)]:
         assert ebc.ebc_compress_bound(rank, dims, ebc.make_params(1e-3, n_bins=nb)) == \
             O.compress_bound(rank, dims, nb)
 

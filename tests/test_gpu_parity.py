@@ -61,6 +61,14 @@ CASES = [
     ("bins4", (64, 64), "grf", 1e-3, "rel", 4),
     ("bins4096", (64, 80), "noise", 1e-4, "rel", 4096),
     ("bins64", (33, 65, 17), "noise", 1e-3, "rel", 64),
+    # above 4096 bins (LDS histogram window + HBM counts, codebook and decoder
+    # tables built in HBM): codes spread over more bins than the window, and
+    # over 35k used symbols at 65536 bins
+    ("bins8192_noise", (96, 120), "noise", 1e-5, "rel", 8192),
+    ("bins65536_noise", (256, 300), "noise", 1e-5, "rel", 65536),
+    ("bins65536_smooth", (256, 256), "grf", 2e-5, "rel", 65536),
+    ("bins16384_3d", (24, 40, 33), "lognormal", 1e-5, "rel", 16384),
+    ("bins32768_1d", (200003,), "walk", 1e-5, "rel", 32768),
 ]
 
 
@@ -389,3 +397,14 @@ def test_huffman_chunks_longer_than_a_pass(E, hc):
     ref = O.compress(xf, 0.5, "abs", codec="huffman", hc=hc)
     a = E.compress(dev(xf), 0.5, "abs", codec="huffman", huff_chunk=hc)
     assert a.cpu().numpy().tobytes() == ref
+
+
+@pytest.mark.parametrize("hc", [64, 8192])
+def test_wide_bins_chunk_sizes(E, hc):
+    """65536 bins with the shortest chunk and with chunks longer than an
+    encode pass (the wide-table variants of both encode paths)."""
+    x = rng_field((256, 300), 15, "noise")
+    ref = O.compress(x, 1e-5, n_bins=65536, codec="huffman", hc=hc)
+    a = E.compress(dev(x), 1e-5, n_bins=65536, codec="huffman", huff_chunk=hc)
+    assert a.cpu().numpy().tobytes() == ref
+    np.testing.assert_array_equal(bits(E.decompress(a).cpu().numpy()), bits(O.decompress(ref)))

@@ -76,6 +76,17 @@ def test_rle_vle_many_runs_and_bins(E):
     assert O.archive_info(ref)["n_a"] > 1_900_000
 
 
+@pytest.mark.parametrize("name,make,eb,nb", [
+    ("3d_lognormal_16384", lambda: synth.lognormal_3d((48, 64, 80), 3), 3e-2, 16384),
+    ("1d_noise_65536", lambda: np.random.default_rng(10).standard_normal(500_001).astype(np.float32),
+     1e-5, 65536),
+], ids=["3d_lognormal_16384", "1d_noise_65536"])
+def test_rle_vle_wide_bins(E, name, make, eb, nb):
+    """Above 4096 bins: the run-value histogram's LDS window and HBM counts,
+    and the second (run-value) codebook built in HBM."""
+    check(E, make(), eb, "rle_vle", n_bins=nb, want_codec=O.ARC_RLE_VLE)
+
+
 def test_rle_vle_in_a_batch(E):
     """Fields of mixed rank through the batched entry point with VLE on: each
     archive equal to the oracle's (codec chosen per field)."""

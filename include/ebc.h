@@ -179,6 +179,26 @@ int ebc_compress_async(const void* d_field, int rank, const uint64_t dims[3],
                        const ebc_params* p, void* d_out, uint64_t out_cap, uint64_t* d_result,
                        void* d_ws, uint64_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+   tight serving loops, hosts that forbid hipMalloc): ebc_compress_async
+   without a workspace argument.  The workspace is a fixed device array of
+   EBC_NOALLOC_SCRATCH_BYTES inside this library; each device the call runs
+   on holds its own copy until the process ends (its address is resolved on
+   the first call on that device, with that device current).  The call
+   allocates no device or page-locked memory (host bookkeeping uses the C++
+   heap).  Arguments, outputs and results are those of ebc_compress_async; the
+   caller still provides d_field, d_out and d_result.
+   Limit: a field whose ebc_compress_workspace_size exceeds the array is
+   rejected with EBC_ERR_WS_TOO_SMALL before any device work (about 6.7 bytes
+   per fp32 element: fields up to roughly 9.5 million values).
+   Every call on one device shares that device's array: calls that overlap in
+   time on one device (streams not ordered after each other) race and give
+   undefined archives.  Calls ordered on one stream are safe. */
+#define EBC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int ebc_compress_async_noalloc(const void* d_field, int rank, const uint64_t dims[3],
+                               const ebc_params* p, void* d_out, uint64_t out_cap,
+                               uint64_t* d_result, void* stream);
+
 /* Parse a host copy of an archive header (at least 128 bytes).  Any output
    pointer may be NULL.  p receives eb mode, eb, n_bins, the Huffman chunk and
    the element type. */

@@ -30,6 +30,7 @@ SOURCES = [
     "k_recon.hip",
     "k_archive.hip",
     "k_estimate.hip",
+    "noalloc.hip",
     "capi.cpp",  # host code only
 ]
 

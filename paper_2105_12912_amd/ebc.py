@@ -35,6 +35,7 @@ CODECS = {"auto": EBC_CODEC_AUTO, "huffman": EBC_CODEC_HUFFMAN, "rle": EBC_CODEC
 EBC_STATS_TIMING = 1
 EBC_MAX_STAGES = 16
 HDR_BYTES = 128
+EBC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed device scratch of ebc_compress_async_noalloc
 
 
 EBC_F32, EBC_F64 = 0, 1
@@ -111,6 +112,7 @@ _SIGS = {
     "ebc_compress_workspace_size": (_I32, [_I32, _P, _P, _P]),
     "ebc_compress": (_I32, [_P, _I32, _P, _P, _P, _U64, _P, _P, _U64, _P, _P]),
     "ebc_compress_async": (_I32, [_P, _I32, _P, _P, _P, _U64, _P, _P, _U64, _P]),
+    "ebc_compress_async_noalloc": (_I32, [_P, _I32, _P, _P, _P, _U64, _P, _P]),
     "ebc_archive_info": (_I32, [_P, _U64, _P, _P, _P, _P, _P]),
     "ebc_decompress_workspace_size": (_I32, [_P, _U64, _P]),
     "ebc_decompress": (_I32, [_P, _U64, _P, _U64, _P, _U64, _P, _P]),
@@ -207,6 +209,12 @@ def ebc_compress_async(d_field, rank, dims, params, d_out, out_cap, d_result, d_
                        stream) -> int:
     return lib().ebc_compress_async(d_field, rank, _dims3(dims), C.byref(params), d_out, out_cap,
                                     d_result, d_ws, ws_bytes, stream)
+
+
+def ebc_compress_async_noalloc(d_field, rank, dims, params, d_out, out_cap, d_result,
+                               stream) -> int:
+    return lib().ebc_compress_async_noalloc(d_field, rank, _dims3(dims), C.byref(params), d_out,
+                                            out_cap, d_result, stream)
 
 
 def ebc_archive_info(header: bytes) -> dict:

@@ -744,7 +744,7 @@ int plan_decompress(Batch& B, const std::vector<DecompressIn>& din, uint8_t* ws)
     B.d_wcnt = bp.take<uint32_t>(4ull * (B.tot_hch + 1));
     B.d_soff = bp.take<uint32_t>(4ull * (B.tot_sub + 1));
     B.d_starts = bp.take<uint32_t>(4ull * (B.tot_runs + 1));
-    B.d_tmap = bp.take<uint32_t>(4ull * (B.tot_rt + 1));
+    B.d_tmap = bp.take<uint32_t>(8ull * (B.tot_rt + 1));  // (first run, run count) per tile
     B.d_tmp = bp.take<uint32_t>(4ull * scan_tmp_words(std::max(B.tot_hch, B.tot_runs)));
     B.max_bins = 0;
     for (int k = 0; k < B.nf; ++k) B.max_bins = std::max(B.max_bins, din[B.order[k]].H.n_bins);

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
             t = skip_field(fd, t) - gridDim.x;  // the loop step adds it back
             continue;
         }
-        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
         uint16_t c[kRleItems];
         const uint32_t flags = run_flags(fd, lo, c);
         uint32_t tot;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_vhist(const FieldDesc* __restric
         const FieldDesc& fd = F[f];
         const auto* dy = kconst(fd.dyn);
         const uint64_t R = dy->n_runs;
-        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
         if (dy->status != ST_OK || dy->codec != ARC_RLE_VLE || lo >= R) {
             t = skip_field(fd, t) - gridDim.x;
             continue;
@@ -247,10 +247,11 @@ __global__ __launch_bounds__(kBlock) void k_rle_check(const FieldDesc* __restric
     if (bad) atomicMin(&fd.dyn->status, ST_ERR_ARCHIVE);
 }
 
-// After the check: the run that holds the first element of every output
-// tile (the largest r with start[r] <= tile start), one thread per tile, so
-// that every tile's search is in flight at once rather than one thread per
-// workgroup searching while the others wait.
+// After the check: for every output tile, the run that holds its first
+// element (the largest r with start[r] <= tile start) and the number of runs
+// it overlaps, one thread per tile, so that every tile's searches are in
+// flight at once rather than one thread per workgroup searching while the
+// others wait.  tmap[2t] = first run, tmap[2t + 1] = run count.
 __global__ __launch_bounds__(kBlock) void k_rle_tilemap(const FieldDesc* __restrict__ F, int nf,
                                                         uint32_t units, const uint32_t* __restrict__ starts,
                                                         uint32_t* __restrict__ tmap)
@@ -263,21 +264,53 @@ __global__ __launch_bounds__(kBlock) void k_rle_tilemap(const FieldDesc* __restr
     const uint32_t* S = starts + fd.rle_base;
     const uint32_t s0 = S[0];
     const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+    const uint64_t hi = min(lo + (uint64_t)kRleTile, fd.n);
     uint32_t a = 0, b = fd.n_runs_hdr - 1;
     while (a < b) {
         const uint32_t m = (a + b + 1) >> 1;
         if ((uint64_t)(S[m] - s0) <= lo) a = m;
         else b = m - 1;
     }
-    tmap[t] = a;
+    uint32_t c = a, d = fd.n_runs_hdr - 1;  // the run holding the tile's last element
+    while (c < d) {
+        const uint32_t m = (c + d + 1) >> 1;
+        if ((uint64_t)(S[m] - s0) <= hi - 1) c = m;
+        else d = m - 1;
+    }
+    tmap[2 * t] = a;
+    tmap[2 * t + 1] = c - a + 1;
+}
+
+// runs of one tile staged in LDS by the expansion (a tile with more runs
+// searches them in HBM)
+constexpr uint32_t kRleStage = 1024;
+
+// The kRleItems codes from element i0 on: the run holding i0 by binary search
+// over the tile's nr run starts (relative to the field), then a forward walk.
+template <class START, class VAL>
+__device__ __forceinline__ void expand_codes(uint64_t i0, uint32_t nr, uint16_t c[kRleItems], START start,
+                                             VAL value)
+{
+    uint32_t a = 0, b = nr - 1;
+    while (a < b) {
+        const uint32_t m = (a + b + 1) >> 1;
+        if ((uint64_t)start(m) <= i0) a = m;
+        else b = m - 1;
+    }
+#pragma unroll
+    for (int k = 0; k < kRleItems; ++k) {
+        const uint64_t i = i0 + k;
+        while (a + 1 < nr && (uint64_t)start(a + 1) <= i) ++a;
+        c[k] = value(a);
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restrict__ F, int nf,
                                                        const uint32_t* __restrict__ starts,
                                                        const uint32_t* __restrict__ tmap)
 {
-    __shared__ uint32_t s_start[kRleTile + 1];
-    __shared__ uint16_t s_val[kRleTile + 1];
+    __shared__ uint32_t s_start[kRleStage];
+    __shared__ uint16_t s_val[kRleStage];
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::rt_base>(F, nf, t);
     const FieldDesc& fd = F[f];
@@ -285,40 +318,26 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     if (dy->status != ST_OK || !rle_codec(fd.codec_hdr)) return;
     const uint32_t* S = starts + fd.rle_base;
     const uint32_t s0 = S[0];
-    const uint32_t R = fd.n_runs_hdr;
     const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
     const uint64_t hi = min(lo + (uint64_t)kRleTile, fd.n);
-    // first run of this tile; its last run is the next tile's first, unless
-    // that one starts exactly at the next tile
-    const uint32_t rlo = tmap[t];
-    uint32_t rlast = R - 1;
-    if (t + 1 < fd.rt_base + fd.n_rt) {
-        const uint32_t r2 = tmap[t + 1];
-        rlast = (uint64_t)(S[r2] - s0) <= hi - 1 ? r2 : r2 - 1;
-    }
-    const uint32_t nr = rlast - rlo + 1;  // <= kRleTile because every run is non-empty
+    const uint32_t rlo = tmap[2 * t], nr = tmap[2 * t + 1];  // nr <= kRleTile: runs are non-empty
     const EBC_G uint16_t* val = fd.rval;
-    for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
-        s_start[i] = S[rlo + i] - s0;
-        s_val[i] = val[rlo + i];
+    const bool staged = nr <= kRleStage;  // uniform over the workgroup
+    if (staged) {
+        for (uint32_t i = threadIdx.x; i < nr; i += kBlock) {
+            s_start[i] = S[rlo + i] - s0;
+            s_val[i] = val[rlo + i];
+        }
     }
     __syncthreads();
     const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
     if (i0 >= hi) return;
-    // run of the first owned element, then walk forward
-    uint32_t a = 0, b = nr - 1;
-    while (a < b) {
-        const uint32_t m = (a + b + 1) >> 1;
-        if ((uint64_t)s_start[m] <= i0) a = m;
-        else b = m - 1;
-    }
     uint16_t c[kRleItems];
-#pragma unroll
-    for (int k = 0; k < kRleItems; ++k) {
-        const uint64_t i = i0 + k;
-        while (a + 1 < nr && (uint64_t)s_start[a + 1] <= i) ++a;
-        c[k] = s_val[a];
-    }
+    if (staged)
+        expand_codes(i0, nr, c, [&](uint32_t k) { return s_start[k]; }, [&](uint32_t k) { return s_val[k]; });
+    else
+        expand_codes(i0, nr, c, [&](uint32_t k) { return S[rlo + k] - s0; },
+                     [&](uint32_t k) { return (uint16_t)val[rlo + k]; });
     EBC_G uint16_t* __restrict__ q = fd.q;
     if (i0 + kRleItems <= hi) {
         uint4 x, y;

@@ -559,14 +559,19 @@ __global__ __launch_bounds__(kBlock) void k_construct(const FieldDesc* __restric
     QuantCtx qc;
     qc.center = 0;
     int cur = -1, par = 0;
+    uint32_t cur_lo = 0, cur_hi = 0;  // tile range of field `cur`
     for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        const int f = find_field<&FieldDesc::wg_base>(F, nf, t);
+        // a workgroup stays in one field for a run of tiles: search the
+        // descriptors only when it leaves the current field's range
+        const int f = t >= cur_lo && t < cur_hi ? cur : find_field<&FieldDesc::wg_base>(F, nf, t);
         const FieldDesc& fd = F[f];
         const auto* dy = kconst(fd.dyn);  // scalar loads: no wait on the previous tile's stores
         if (dy->status != ST_OK || dy->codec == ARC_CONST) continue;  // uniform over the workgroup
         if (f != cur) {
             if (cur >= 0) flush_hist<WIDE>(F[cur], qc, sh_hist);
             cur = f;
+            cur_lo = fd.wg_base;
+            cur_hi = fd.wg_base + fd.wg_tiles;
             qc.inv = dy->inv;
             qc.r = (int32_t)(nb / 2);
             qc.lo = hist_win_lo(nb);

@@ -123,11 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_rle_write(const FieldDesc* __restric
             t = skip_field(fd, t) - gridDim.x;  // the loop step adds it back
             continue;
         }
-    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+        // the tile's output offset is loaded before its codes, so its latency
+        // overlaps theirs
+        const uint32_t base = roff[t] - roff[fd.rt_base];
         uint16_t c[kRleItems];
         const uint32_t flags = run_flags(fd, lo, c);
         uint32_t tot;
-        uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + (roff[t] - roff[fd.rt_base]);
+        uint32_t pos = block_excl_scan_rle(__popc(flags), &tot) + base;
         EBC_G uint16_t* val = val_arc ? (EBC_G uint16_t*)(fd.arc + kHdr) : fd.vsym;
         const uint64_t i0 = lo + (uint64_t)threadIdx.x * kRleItems;
 #pragma unroll
@@ -165,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_rle_vhist(const FieldDesc* __restric
         const FieldDesc& fd = F[f];
         const auto* dy = kconst(fd.dyn);
         const uint64_t R = dy->n_runs;
-    const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
+        const uint64_t lo = (uint64_t)(t - fd.rt_base) * kRleTile;
         if (dy->status != ST_OK || dy->codec != ARC_RLE_VLE || lo >= R) {
             t = skip_field(fd, t) - gridDim.x;
             continue;

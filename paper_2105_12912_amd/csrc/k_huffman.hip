@@ -722,7 +722,9 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                 buf |= need ? ((uint64_t)nxt << ((32u - valid) & 63u)) : 0ull;
                 valid += need ? 32u : 0u;
                 wr.rd += need ? 1u : 0u;
-                nxt = wr.peek();
+                // only lanes that took a word read the next one (fewer LDS bank
+                // accesses; the word at rd is in the ring by the refill schedule)
+                if (need) nxt = wr.peek();
             }
             const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
             const uint32_t eh = (uint32_t)(e >> 32);
@@ -747,10 +749,17 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                 tl = L;
                 s01 = sym;
             }
-            // three symbol slots; only the decoded ones are kept (sp <= kCap)
-            row16[sp] = (uint16_t)s01;
-            row16[sp + 1] = (uint16_t)(s01 >> 16);
-            row16[sp + 2] = (uint16_t)s2;
+            // the step's three symbol slots (only the decoded ones are kept;
+            // sp <= kCap) in two LDS stores: the dword at halfword
+            // (sp + 1) & ~1 and the halfword left over.  The LDS pipe, not the
+            // VALU, bounds this loop: three halfword stores took 14% longer at
+            // rel 1e-4, and one store of two dwords (with the previous symbol
+            // kept in a register) was no faster than three.
+            {
+                const bool odd = (sp & 1u) != 0;
+                row[(sp + 1) >> 1] = odd ? (s01 >> 16) | (s2 << 16) : s01;
+                row16[odd ? sp : sp + 2] = (uint16_t)(odd ? s01 : s2);
+            }
             const uint32_t left = want - j;
             if (act && n > left) {
                 // the lane's last symbols take only the leading codewords

@@ -160,3 +160,27 @@ def test_tuning_never_changes_bytes(E, fields, oracle_arcs, wx, grid, scan):
                                           ref.view(np.uint32).ravel())
     finally:
         assert E.ebc_set_tuning([]) == 0
+
+
+def test_batch_decompress_mixed_bin_counts(E):
+    """One batched decompression over archives of different bin counts (64,
+    1024, 8192, 65536; Huffman and RLE+VLE): narrow and wide decoder tables
+    are built in the same call at the stride of the widest."""
+    from paper_2105_12912_amd.batch import BatchDecompress
+
+    rng = np.random.default_rng(21)
+    cases = [
+        (synth.smooth_2d(96, 130, 3), 1e-4, 64, "huffman"),
+        (rng.standard_normal((200, 150)).astype(np.float32), 1e-5, 65536, "huffman"),
+        (synth.lognormal_3d((24, 40, 33), 5), 1e-3, 1024, "auto"),
+        (synth.random_walk_1d(300_001, 8), 1e-5, 8192, "huffman"),
+        (synth.lognormal_3d((32, 48, 40), 6), 3e-2, 16384, "rle_vle"),
+    ]
+    refs = [O.compress(x, eb, n_bins=nb, codec=c) for x, eb, nb, c in cases]
+    arcs = [torch.from_numpy(np.frombuffer(a, dtype=np.uint8).copy()).cuda() for a in refs]
+    D = BatchDecompress(arcs)
+    D.launch()
+    assert D.statuses() == [0] * len(arcs)
+    for i, (y, a) in enumerate(zip(D.outs, refs)):
+        np.testing.assert_array_equal(y.cpu().numpy().view(np.uint32).ravel(),
+                                      O.decompress(a).view(np.uint32).ravel(), err_msg=f"field {i}")

@@ -356,10 +356,16 @@ __global__ __launch_bounds__(kBlock) void k_rle_expand(const FieldDesc* __restri
     }
 }
 
+// The two encode passes stream the codes with a grid the device holds whole
+// (8 workgroups of 256 per CU): with half that many workgroups in flight the
+// count and write stages on a 1.2e8-value field took 75 and 101 us instead
+// of 63 and 81.
+constexpr uint32_t kRleBlocks = 2048;
+
 hipError_t launch_rle_count(const FieldDesc* F, int nf, uint32_t units, uint32_t* rcnt, hipStream_t s)
 {
     if (!units) return hipSuccess;
-    const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
+    const uint32_t g = units < kRleBlocks ? units : kRleBlocks;
     hipLaunchKernelGGL(k_rle_count, dim3(g), dim3(kBlock), 0, s, F, nf, rcnt, units);
     return hipGetLastError();
 }
@@ -368,7 +374,7 @@ hipError_t launch_rle_write(const FieldDesc* F, int nf, uint32_t units, const ui
                             hipStream_t s)
 {
     if (!units) return hipSuccess;
-    const uint32_t g = units < kPersistentBlocks ? units : kPersistentBlocks;
+    const uint32_t g = units < kRleBlocks ? units : kRleBlocks;
     hipLaunchKernelGGL(k_rle_write, dim3(g), dim3(kBlock), 0, s, F, nf, roff, units, what);
     return hipGetLastError();
 }

@@ -43,6 +43,9 @@ CASES = [
     ("3d_ragged", (9, 10, 11), "smooth", 1e-4, 1024),
     ("3d_noise", (24, 40, 33), "noise", 1e-4, 64),
     ("2d_noise", (70, 90), "noise", 1e-7, 4096),
+    # above 4096 bins: histogram window, codebook and tables in HBM
+    ("2d_noise_65536", (200, 150), "noise", 1e-7, 65536),
+    ("3d_smooth_16384", (24, 40, 33), "smooth", 1e-8, 16384),
 ]
 
 

@@ -37,7 +37,7 @@ def compress_both(E, x, eb):
     """The same field through both entry points on the current stream;
     returns the two archives as bytes."""
     rank, dims = E.field_rank_dims(x)
-    p = E.make_params(eb)
+    p = E.make_params(eb, dtype=E._dtype_code(x))
     bound = E.ebc_compress_bound(rank, dims, p)
     stream = E._stream_handle()
     out_a = torch.empty(bound, dtype=torch.uint8, device=x.device)
@@ -68,13 +68,16 @@ def test_noalloc_matches_workspace_entry_point(E):
         ("2D 1800x3600 rel 1e-4", synth.climate_2d(), 1e-4),
         ("3D 96^3 lognormal rel 1e-3", synth.lognormal_3d((96, 96, 96), 31), 1e-3),
         ("2D 256x256 rel 1e-4", synth.smooth_2d(256, 256, 1), 1e-4),
+        ("2D 128x160 fp64 rel 1e-7", synth.smooth_2d(128, 160, 2).astype(np.float64) * 1e3, 1e-7),
     ]
-    sizes = [x.size for _, x, _ in fields]
+    sizes = [x.nbytes for _, x, _ in fields]
     assert sizes == sorted(sizes, reverse=True)  # each call smaller than the one before
     for label, x, eb in fields:
         print(f"[noalloc] {label}", flush=True)
-        rank, dims = E.field_rank_dims(torch.empty(x.shape, device="meta"))
-        need = E.ebc_compress_workspace_size(rank, dims, E.make_params(eb))
+        xm = torch.empty(x.shape, dtype=torch.float64 if x.dtype == np.float64 else torch.float32,
+                         device="meta")
+        rank, dims = E.field_rank_dims(xm)
+        need = E.ebc_compress_workspace_size(rank, dims, E.make_params(eb, dtype=E._dtype_code(xm)))
         assert need <= E.EBC_NOALLOC_SCRATCH_BYTES
         a, b = compress_both(E, torch.from_numpy(x).cuda(), eb)
         assert a == b

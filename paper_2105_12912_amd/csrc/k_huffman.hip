@@ -627,13 +627,24 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                                                           const uint8_t* __restrict__ tabs,
                                                           size_t tab_stride)
 {
-    __shared__ uint64_t lut[1u << kLutBits];
-    __shared__ uint32_t l2s[kL2Size];
-    __shared__ uint64_t s_first[65];
-    __shared__ uint64_t s_endv[65];
-    __shared__ uint32_t s_off[65];
-    __shared__ uint32_t s_ring[kDecLanes * kRingStride];
-    __shared__ uint32_t s_stage[kDecLanes * kStageWords];
+    // one block so that the table sits at LDS address 0 (its index needs no base)
+    struct Lds {
+        uint64_t lut[1u << kLutBits];
+        uint64_t first[65];
+        uint64_t endv[65];
+        uint32_t l2s[kL2Size];
+        uint32_t off[65];
+        uint32_t ring[kDecLanes * kRingStride];
+        uint32_t stage[kDecLanes * kStageWords];
+    };
+    __shared__ Lds sm;
+    uint64_t* const lut = sm.lut;
+    uint32_t* const l2s = sm.l2s;
+    uint64_t* const s_first = sm.first;
+    uint64_t* const s_endv = sm.endv;
+    uint32_t* const s_off = sm.off;
+    uint32_t* const s_ring = sm.ring;
+    uint32_t* const s_stage = sm.stage;
     const uint32_t t = blockIdx.x;
     const int f = find_field<&FieldDesc::hdwg_base>(F, nf, t);
     const FieldDesc& fd = F[f];
@@ -686,28 +697,34 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
     buf <<= skip;
     uint32_t valid = 64 - skip;
     uint32_t j = 0, sp = 0, flushed = 0;
+    uint32_t nflush = 0;  // flushes the wave has made
     bool slow = false;
     bool act = want > 0;
     uint32_t nxt = wr.peek();
     // a block of kFlush symbols leaves when every lane still decoding has one
     auto flush = [&]() {
         if (__all(sp >= kFlush || !act)) {
+            // every lane holding a block has taken part in every flush so far
+            // (a lane left out had stopped decoding with fewer than kFlush
+            // symbols and never gains more), so its offset is wave-uniform
+            const uint64_t has = ballot(sp >= kFlush);
+            const uint32_t flw = (uint32_t)__builtin_amdgcn_readfirstlane((int)(nflush * kFlush));
 #pragma unroll
             for (uint32_t k = 0; k < kParts; ++k) {
                 const uint32_t piece = k * kWave + lane;
                 const uint32_t L = piece / kParts, part = piece % kParts;
-                const uint32_t spL = (uint32_t)__shfl((int)sp, (int)L);
-                const uint32_t flL = (uint32_t)__shfl((int)flushed, (int)L);
-                if (spL >= kFlush) {
+                if ((has >> L) & 1u) {
                     const uint32_t* src = wave_rows + L * kStageWords + part * 4;
                     const uint4 v = make_uint4(src[0], src[1], src[2], src[3]);
-                    *(EBC_G uint4*)(fd.hsym + (uint64_t)(sub0 + L) * hs + flL + part * 8) = v;
+                    *(EBC_G uint4*)(fd.hsym + (uint64_t)(sub0 + L) * hs + flw + part * 8) = v;
                 }
             }
+            ++nflush;
             if (sp >= kFlush) {
-                // the symbols past the block move to the front of the row
+                // the symbols past the block (at most kCap - kFlush) move to
+                // the front of the row
 #pragma unroll
-                for (uint32_t w = 0; w < kStageWords - kFlush / 2; ++w) row[w] = row[kFlush / 2 + w];
+                for (uint32_t w = 0; w < (kCap - kFlush + 1) / 2; ++w) row[w] = row[kFlush / 2 + w];
                 sp -= kFlush;
                 flushed += kFlush;
             }
@@ -757,14 +774,19 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
             // kept in a register) was no faster than three.
             {
                 const bool odd = (sp & 1u) != 0;
-                row[(sp + 1) >> 1] = odd ? (s01 >> 16) | (s2 << 16) : s01;
-                row16[odd ? sp : sp + 2] = (uint16_t)(odd ? s01 : s2);
+                // the halfword sits just before (odd sp) or just after the dword
+                uint32_t* const dw = (uint32_t*)((char*)row + ((2 * sp + 2) & ~3u));
+                *dw = odd ? (s01 >> 16) | (s2 << 16) : s01;
+                *(uint16_t*)((char*)dw + (odd ? -2 : 4)) = (uint16_t)(odd ? s01 : s2);
             }
             const uint32_t left = want - j;
-            if (act && n > left) {
-                // the lane's last symbols take only the leading codewords
+            if (__builtin_expect(act && n > left, 0)) {
+                // the lane's last symbols take only the leading codewords (the
+                // bit count is checked against the sub-chunk's); a branch taken
+                // once per lane, kept out of the step by the empty asm
                 tl = ((eh >> 24) & 15u) + (left == 2 ? eh >> 28 : 0u);
                 n = left;
+                asm volatile("" ::: "memory");
             }
             const bool go = act && sp + 3 <= kCap;
             n = go ? n : 0u;

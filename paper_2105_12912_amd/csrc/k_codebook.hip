@@ -684,7 +684,11 @@ __device__ __forceinline__ void dectab_tables(DecTab* T, const uint32_t* cntL, c
     }
     __syncthreads();
     // Second level: number the prefixes that start a longer codeword, give
-    // each a block of 2^k entries resolving the next k bits.
+    // each a block of 2^k entries resolving the next k bits.  Longer codewords
+    // are numerically larger (the limit test above), so these prefixes are the
+    // top nlong ones and the numbering in prefix order makes a block's start
+    // (p - (2^kLutBits - nlong)) << k: the decoder computes the second-level
+    // index from the stream bits alone and relies on this order.
     __shared__ uint16_t lslot[1u << kLutBits];
     __shared__ uint16_t lpref[1u << kLutBits];
     __shared__ uint32_t s_wsum[kCbWaves];

@@ -653,6 +653,7 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
     const DecTab* __restrict__ T = (const DecTab*)(tabs + (size_t)f * tab_stride);
     for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += kDecLanes) lut[i] = T->lut[i];
     const uint32_t l2k = T->l2k, l2n = T->l2n;
+    const uint32_t l2sub = (1u << (kLutBits + l2k)) - l2n;  // first long prefix << l2k
     for (uint32_t i = threadIdx.x; i < l2n; i += kDecLanes) l2s[i] = T->l2[i];
     if (threadIdx.x < 65) {
         s_first[threadIdx.x] = T->first[threadIdx.x];
@@ -743,8 +744,18 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                 // accesses; the word at rd is in the ring by the refill schedule)
                 if (need) nxt = wr.peek();
             }
+            // the prefixes that start a codeword longer than the table are the
+            // top nlong ones and own consecutive blocks in prefix order, so the
+            // second-level index follows from the bits alone and its read
+            // overlaps the table's (clamped: other lanes read entry 0)
+            uint32_t i2 = ((uint32_t)(buf >> 32) >> (32 - kLutBits - l2k)) - l2sub;
+            i2 = i2 < l2n ? i2 : 0u;
+            const uint32_t v2 = l2s[i2];
             const uint64_t e = lut[(uint32_t)(buf >> (64 - kLutBits))];
             const uint32_t eh = (uint32_t)(e >> 32);
+            // keeps the read above the branch; LDS reads return in order, so
+            // the wait for the table entry covers it
+            asm volatile("" ::"v"(v2), "v"(eh));
             uint32_t n = (eh >> 16) & 3u;
             uint32_t tl = (eh >> 18) & 63u;
             uint32_t s01 = (uint32_t)e, s2 = eh & 0xFFFFu;
@@ -753,7 +764,7 @@ __global__ __launch_bounds__(kDecLanes) void k_huff_decode(const FieldDesc* __re
                 uint32_t sym = 0, L = 0;
                 const uint32_t base = (uint32_t)e & 0xFFFFu;
                 if (base != 0xFFFFu) {
-                    const uint32_t v = l2s[base + (uint32_t)((buf << kLutBits) >> (64 - l2k))];
+                    const uint32_t v = v2;
                     L = v >> 16;
                     sym = v & 0xFFFFu;
                 }

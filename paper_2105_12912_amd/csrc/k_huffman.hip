@@ -180,10 +180,16 @@ struct BitsProc {
         // issued before any is used
         const uint32_t m = lo < u.cnt ? (uint32_t)min<uint64_t>(S, u.cnt - lo) : 0u;
         uint32_t bits = 0;
+        if (__all(m == S)) {
+            // every lane holds S symbols (all chunks but a field's last)
 #pragma unroll
-        for (uint32_t k = 0; k < S; ++k) {
-            const uint32_t L = W ? fd.len[k < m ? r.at(k) : 0u] : len_s[k < m ? r.at(k) : 0u];
-            bits += k < m ? L : 0u;
+            for (uint32_t k = 0; k < S; ++k) bits += W ? fd.len[r.at(k)] : len_s[r.at(k)];
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < S; ++k) {
+                const uint32_t L = W ? fd.len[k < m ? r.at(k) : 0u] : len_s[k < m ? r.at(k) : 0u];
+                bits += k < m ? L : 0u;
+            }
         }
         bits = wave_sum_u32(bits);
         if (lane_id() == 0) {
@@ -283,14 +289,26 @@ struct WriteProc {
         const uint32_t m = live && lo < u.cnt ? (uint32_t)min<uint64_t>(S, u.cnt - lo) : 0u;
         uint64_t e[kKeep ? S : 1];
         uint32_t mybits = 0, lmax = 0;
+        if (__all(m == S)) {
+            // every lane holds S symbols (all chunks but a field's last)
 #pragma unroll
-        for (uint32_t k = 0; k < S; ++k) {
-            const uint64_t v0 = entry(fd, code_s, k < m ? r.at(k) : 0u);
-            const uint64_t v = k < m ? v0 : 0ull;
-            if (kKeep) e[kKeep ? k : 0] = v;
-            const uint32_t L = (uint32_t)v & 0xFFu;
-            mybits += L;
-            lmax = max(lmax, L);
+            for (uint32_t k = 0; k < S; ++k) {
+                const uint64_t v = entry(fd, code_s, r.at(k));
+                if (kKeep) e[kKeep ? k : 0] = v;
+                const uint32_t L = (uint32_t)v & 0xFFu;
+                mybits += L;
+                lmax = max(lmax, L);
+            }
+        } else {
+#pragma unroll
+            for (uint32_t k = 0; k < S; ++k) {
+                const uint64_t v0 = entry(fd, code_s, k < m ? r.at(k) : 0u);
+                const uint64_t v = k < m ? v0 : 0ull;
+                if (kKeep) e[kKeep ? k : 0] = v;
+                const uint32_t L = (uint32_t)v & 0xFFu;
+                mybits += L;
+                lmax = max(lmax, L);
+            }
         }
         for (uint32_t i = lane_id(); i < nw; i += kWave) wbuf[i] = 0;
         uint32_t sb = 0;

@@ -104,6 +104,38 @@ def test_canonical_codes_prefix_free_and_ordered(h):
             assert code[b] == code[a] + 1
 
 
+@pytest.mark.parametrize("w", (4, 8, 12))
+@pytest.mark.parametrize("h", HISTS, ids=lambda h: f"nb{h.size}")
+def test_long_codeword_prefixes_are_the_top_ones(h, w):
+    """A decoder that looks up w bits at a time can index its second-level
+    table from the bits alone when the w-bit prefixes that start a codeword
+    longer than w are the top ones, numbered in prefix order. Canonical codes
+    (longer codewords numerically larger) make it so: every w-bit prefix is
+    covered by exactly one codeword of length <= w or starts a longer one,
+    and the latter form the range [2^w - nlong, 2^w)."""
+    ln = O.huffman_lengths(h)
+    code = O.canonical_codes(ln)
+    covered = np.zeros(1 << w, dtype=np.int64)
+    long_pref = set()
+    for s in range(h.size):
+        L = int(ln[s])
+        if L == 0:
+            continue
+        c = int(code[s])
+        if L <= w:
+            base = c << (w - L)
+            covered[base:base + (1 << (w - L))] += 1
+        else:
+            long_pref.add(c >> (L - w))
+    assert covered.max(initial=0) <= 1
+    if int((ln > 0).sum()) < 2:
+        assert not long_pref  # a lone symbol has a 1-bit code
+        return
+    nlong = (1 << w) - int(covered.sum())
+    assert long_pref == set(range((1 << w) - nlong, 1 << w))
+    assert not covered[(1 << w) - nlong:].any()
+
+
 @pytest.mark.parametrize("h", HISTS, ids=lambda h: f"nb{h.size}")
 def test_redundancy_bounds(h):
     """H <= <b> <= H + p1 + 0.086, and <b> >= H + 1 - H(p1, 1-p1) for p1 > 0.4."""
